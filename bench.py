@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark of the 2D EM-PIC step on one MI355X.
+
+A step is one pass of the whole hot path over the resident simulation:
+interpolate + Boris push + charge-conserving deposit (k_push_deposit), tile
+hand-off (k_migrate), current fold, binomial filter, Yee field advance and the
+step bookkeeping.  The default workload is the two counter-streaming electron
+clouds on a periodic 1024 x 1024 grid (16,777,216 particles, 16 per cell per
+species), whose particle arrays (0.4 GB read and written per step) are larger
+than the 256 MB Infinity Cache, so the push kernel streams from HBM.
+
+Prints one JSON line: whole-job throughput in particle pushes per second over
+K timed steps (inputs resident in HBM), the roofline of the dominant kernel
+(k_push_deposit, HBM-bound) from HIP events, step-latency percentiles and the
+FP64 CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = ("particle pushes/sec (push+deposit, FP32) vs HBM roofline; "
+          "p50/p99 batched step latency")
+
+# algorithmic HBM bytes of k_push_deposit: per particle the state read and
+# written once (packed cell int32 + x, y, ux, uy, uz), per cell the six field
+# components read once and the three current components written once
+BYTES_PER_PARTICLE = {False: 2 * (4 + 5 * 4), True: 2 * (4 + 5 * 8)}
+BYTES_PER_CELL = {False: (6 + 3) * 4, True: (6 + 3) * 8}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="clouds_1024x1024")
+    ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="warm-up and timed steps only (for rocprofv3)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, nsteps):
+    """Time the FP64 oracle (single-threaded C) on the same workload: its own
+    load, then nsteps full steps."""
+    from oracle import OracleSim, Species
+    o = OracleSim(w.nx, w.ny, w.lx, w.ly, w.dt, window=w.moving_window,
+                  filter_passes=w.filter_passes, filter_compensate=w.filter_compensate,
+                  seed=w.seed)
+    for s in w.species:
+        o.add_species(Species(s.qm, s.density, s.x_lo, s.x_hi, s.ppc, s.uth, s.ufl))
+    if w.laser is not None:
+        L = w.laser
+        o.add_laser(L.a0, L.omega0, L.W0, L.fwhm, L.x_center, L.focus, L.axis, L.pol)
+    n = sum(o.count(k) for k in range(len(w.species)))
+    t0 = time.perf_counter()
+    o.step(nsteps)
+    dt = time.perf_counter() - t0
+    return dict(value=n * nsteps / dt, unit="particle pushes/s", cores=1, kind="oracle",
+                sample="%d full steps of %s from its initial load (%d particles), FP64, "
+                       "one thread" % (nsteps, w.name, n),
+                seconds=round(dt, 3))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from inputs import WORKLOADS
+    from paper_2106_12485_amd import Simulation
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]()
+    sim = Simulation(w, fp64=args.fp64)
+    nparts = sum(sim.count(k) for k in range(len(w.species)))
+    stream = sim.stream
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    # timed region: K steps replayed from the captured step graph
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if args.profile_only:
+        print(json.dumps(dict(steps=args.steps, ms_per_step=(t1 - t0) * 1e3 / args.steps)))
+        return
+    n_end = sum(sim.count(k) for k in range(len(w.species)))
+    status = sim.status()
+    elapsed = t1 - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = nparts * args.steps / elapsed
+
+    # per-kernel split over the same number of steps, HIP events recorded on
+    # the stream the kernels run on
+    sim.timing(True)
+    sim.step(args.steps)
+    tk = sim.timing_read()
+    sim.timing(False)
+    ms_push, n_push = tk["push_deposit"]
+    avg_push_s = ms_push / max(n_push, 1) * 1e-3
+    ncell = w.nx * w.ny
+    alg_bytes = nparts * BYTES_PER_PARTICLE[args.fp64] + ncell * BYTES_PER_CELL[args.fp64]
+    achieved = alg_bytes / avg_push_s / 1e9
+
+    # per-step latency distribution (events around each replayed step)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    for k in range(args.steps):
+        starts[k].record(stream)
+        sim.step(1)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+
+    line = dict(
+        metric=METRIC, value=value, unit="particle pushes/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64" if args.fp64 else "f32", data="synthetic",
+        config=dict(workload=w.name, cells="%dx%d" % (w.nx, w.ny), particles=int(nparts),
+                    species=len(w.species), ppc_per_species=w.species[0].ppc[0] *
+                    w.species[0].ppc[1], dt=w.dt, filter_passes=w.filter_passes,
+                    moving_window=w.moving_window),
+        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                      kernel="k_push_deposit", avg_launch_ms=round(avg_push_s * 1e3, 4),
+                      alg_bytes_per_launch=int(alg_bytes),
+                      pushes_per_s_kernel=nparts / avg_push_s),
+        kernel_ms_per_step={k: round(v[0] / max(v[1], 1), 4) for k, v in tk.items() if v[1]},
+        latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 4),
+                        p99=round(float(np.percentile(lat, 99)), 4)),
+        particles_end=int(n_end), status=int(status),
+    )
+    if args.cpu_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * pic.h -- C ABI of libpic, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of one timestep of the 2D electromagnetic
+ * particle-in-cell (EM-PIC) cycle studied in "Particle-In-Cell Simulation
+ * using Asynchronous Tasking" (Guidotti et al., arXiv 2106.12485).
+ *
+ * The cycle (paper Sec. 2.2, Fig. 1):
+ *   stage 1  bilinear interpolation of the previous-iteration E, B to each
+ *            particle;
+ *   stage 2  leapfrog + relativistic Boris momentum/position advance;
+ *   stage 3  exact charge-conserving (Villasenor-Buneman) current deposition,
+ *            optionally smoothed by a binomial digital filter;
+ *   stage 4  Yee-mesh FDTD advance of E and B.
+ * The paper's spatial decomposition into regions with ghost cells and
+ * particle transfer between neighbouring regions (Sec. 3.2) appears here as
+ * GPU tiles: each tile owns a particle segment, stages fields and current in
+ * LDS with a guard halo, and hands leaving particles to its neighbours.
+ * Sec. 4.1 adds a moving window, laser-initialised fields, a compensated
+ * binomial filter and immobile neutralising ions.
+ *
+ * Conventions
+ *   - Normalised units: c = 1, time in 1/w_p, length in c/w_p, momenta as
+ *     proper velocity u = gamma v, fields in m c w_p / e, charge density in
+ *     units of e n_0; dE/dt = curl B - J, dB/dt = -curl E, div E = rho.
+ *   - Yee staggering: Ex(i+1/2, j) Ey(i, j+1/2) Ez(i, j) Bx(i, j+1/2)
+ *     By(i+1/2, j) Bz(i+1/2, j+1/2); J_k sits with E_k; E and B are both
+ *     held at integer time.
+ *   - Host field planes are row-major (ny, nx) arrays, x fastest; element
+ *     [j*nx + i] is the value at the component's own position next to cell
+ *     (i, j).  Planes are ordered Ex Ey Ez Bx By Bz (fields) and Jx Jy Jz
+ *     (current).  With a moving window, host cell indices are window
+ *     coordinates.
+ *   - A particle is a cell index (ix, iy) plus an in-cell offset x, y in
+ *     [0, 1) and a momentum (ux, uy, uz); its position is ((ix+x)dx, (iy+y)dy).
+ *   - Every call returns 0 (PIC_OK) or a negative PIC_E_* code; no C++
+ *     exception crosses the ABI.  pic_strerror() names a code and
+ *     pic_last_error() returns the most recent detailed message.
+ *   - Device memory is a caller-owned arena (any device allocation, e.g. a
+ *     torch uint8 tensor) of at least pic_mem_bytes() bytes; the library
+ *     sub-allocates everything from it and allocates no device memory of its
+ *     own.  Host pointers passed in are only read during the call; host
+ *     output buffers are caller-owned.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is ordered on it; calls that return host data
+ *     synchronise it.  A simulation handle must be used from one stream at a
+ *     time.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_SPECIES 4
+
+enum {
+    PIC_OK = 0,
+    PIC_E_ARG = -1,      /* invalid argument or configuration */
+    PIC_E_CFL = -2,      /* dt violates the 2D Courant limit */
+    PIC_E_NOMEM = -3,    /* arena smaller than pic_mem_bytes() */
+    PIC_E_CAPACITY = -4, /* a tile or outbox ran out of particle slots */
+    PIC_E_HIP = -5,      /* a HIP runtime call failed */
+    PIC_E_STATE = -6     /* call not valid in the handle's current state */
+};
+
+typedef struct pic_sim pic_sim;
+
+/* One particle species, loaded on a lattice of ppc_x * ppc_y sub-cell centres
+ * ((m + 1/2)/ppc_x, (l + 1/2)/ppc_y) per cell, wherever the lab-frame x of
+ * the particle, ((lab cell) + (m + 1/2)/ppc_x) * dx evaluated in double,
+ * lies in [x_lo, x_hi).  Momenta are u = ufl + uth * N(0, 1) per component,
+ * the normals drawn by Box-Muller from Philox4x32-10 (Salmon et al., SC'11)
+ * with key = (seed low word, seed high word) and counter =
+ * (lab cell x, cell y, l * ppc_x + m, species index).  Each macro-particle
+ * carries charge sign(q_over_m) * density / (ppc_x * ppc_y), so a uniform
+ * load deposits |rho| = density. */
+typedef struct {
+    double q_over_m;
+    double density;
+    double x_lo, x_hi;
+    int ppc_x, ppc_y;
+    double uth[3];
+    double ufl[3];
+} pic_species_cfg;
+
+/* Initial laser (paper Sec. 4.1: fields start with the laser's values): a 2D
+ * paraxial Gaussian beam travelling along +x,
+ *   E_perp = a0 w0 g(x) sqrt(W0/w(z)) exp(-r^2/w^2)
+ *            cos(w0 (x - x_center) + w0 r^2 / (2 R(z)) - atan(z/zR)/2),
+ *   z = x - focus, r = y - axis, zR = w0 W0^2 / 2, w = W0 sqrt(1 + z^2/zR^2),
+ *   R = z (1 + zR^2/z^2), g = exp(-2 ln2 (x - x_center)^2 / fwhm^2) cut to 0
+ * where |x - x_center| > 2 fwhm; (Ey, Ez) = E_perp (cos pol, sin pol) and
+ * (By, Bz) = (-Ez, Ey), each evaluated at its own staggered position. */
+typedef struct {
+    int on;
+    double a0, omega0, W0, fwhm, x_center, focus, axis, pol_angle;
+} pic_laser_cfg;
+
+typedef struct {
+    int nx, ny;          /* cells; each >= 2 and <= 32767, and n % 16 != 1 */
+    double lx, ly;       /* box size; dx = lx/nx, dy = ly/ny */
+    double dt;           /* must satisfy dt < 1/sqrt(1/dx^2 + 1/dy^2) */
+    int moving_window;   /* 1: the box follows +x at c (x not periodic) */
+    int filter_passes;   /* binomial 1-2-1 passes per axis (0 = no filter) */
+    int filter_compensate; /* 1: compensator (-N, 4+2N, -N)/4 after them */
+    int n_species;       /* 0 .. PIC_MAX_SPECIES */
+    pic_species_cfg sp[PIC_MAX_SPECIES];
+    pic_laser_cfg laser;
+    int fp64;            /* 0: FP32 particles/fields/current, 1: FP64 */
+    unsigned long long seed;
+    int load;            /* 1: load every species at init, 0: start empty */
+    double capacity_factor; /* particle slots per tile = factor * ppc * 256
+                               (0 selects 3.0) */
+} pic_cfg;
+
+/* Diagnostics in FP64 (stage a9).  Energies are integrals over the box:
+ * e_energy = sum (E^2)/2 dx dy, b_energy = sum (B^2)/2 dx dy at the current
+ * time n; ke[s] = sum m_p |u-|^2/(gamma- + 1) dx dy with
+ * u- = u^{n-1/2} + (q/m)(dt/2) E^n(x^n) and m_p = q_p/(q/m).
+ * gauss_res_max = max over nodes of |div E^n - F rho^n - (div E^0 - F rho^0)|
+ * (F = the current filter; zero up to round-off on periodic boxes).
+ * cont_res_max = max over nodes of |(rho^n - rho^{n-1})/dt + div J^{n-1/2}|
+ * with the unfiltered current of the last step; it is available only when the
+ * previous pic_energy call was exactly one step earlier, else it is -1. */
+typedef struct {
+    double e_energy, b_energy;
+    double ke[PIC_MAX_SPECIES];
+    double total;
+    double charge;            /* sum of q_p over particles times dx dy */
+    double gauss_res_max;
+    double cont_res_max;
+    double rho_max;           /* max |rho^n| (scale for the residuals) */
+    double t;
+    long long n_particles[PIC_MAX_SPECIES];
+    long long step;
+    int nshift;               /* moving-window shifts done */
+    int status;               /* device error state, as pic_status() */
+} pic_diag;
+
+/* Bytes of device arena that pic_init needs for this configuration, or 0 if
+ * the configuration is invalid (pic_last_error() says why). */
+size_t pic_mem_bytes(const pic_cfg *cfg);
+
+/* Validate cfg, lay the simulation out in `arena` (device memory, at least
+ * pic_mem_bytes(cfg) bytes, 256-byte aligned, owned by the caller and kept
+ * alive until pic_free), zero it, write the laser fields and load the
+ * species (cfg->load).  Returns PIC_E_CFL if dt breaks the Courant limit,
+ * PIC_E_NOMEM if the arena is too small, PIC_E_CAPACITY if the initial load
+ * does not fit.  Synchronises `stream`.  On success *out owns host state. */
+int pic_init(const pic_cfg *cfg, void *arena, size_t arena_bytes, void *stream,
+             pic_sim **out);
+
+/* Stages 1-3 plus the particle hand-off between tiles (hot-path rows a1-a4):
+ * interpolate E^n, B^n to every particle, Boris push to u^{n+1/2}, move, and
+ * deposit the Villasenor-Buneman current of the move into per-tile blocks;
+ * then migrate the particles that left their tile.  Asynchronous on stream. */
+int pic_deposit(pic_sim *sim, void *stream);
+
+/* Rows a5-a8: fold the per-tile current blocks into the global current
+ * (periodic wrap, or drop beyond the moving window), apply the filter, advance
+ * E, B by one Yee step (B half, E full, B half) and, with the moving window,
+ * shift the window by one cell once the light front has crossed the next
+ * cell boundary (iter*dt >= (nshift+1)*dx in double), removing the particles
+ * of the column that leaves and loading the column that enters.
+ * Asynchronous on stream. */
+int pic_field_advance(pic_sim *sim, void *stream);
+
+/* nsteps times (pic_deposit; pic_field_advance).  After the first call the
+ * step is replayed from a captured HIP graph.  Asynchronous on stream. */
+int pic_step(pic_sim *sim, int nsteps, void *stream);
+
+/* FP64 diagnostics of the current state (see pic_diag).  Synchronises. */
+int pic_energy(pic_sim *sim, pic_diag *out, void *stream);
+
+/* Device error state accumulated so far: PIC_OK or PIC_E_CAPACITY (a tile or
+ * an outbox overflowed; the excess particles were dropped and the run is no
+ * longer valid).  Synchronises. */
+int pic_status(pic_sim *sim, void *stream);
+
+/* Release the host state.  The arena stays the caller's. */
+int pic_free(pic_sim *sim);
+
+/* Replace all particles of species sp with n particles given as host arrays
+ * (ix in [0, nx), iy in [0, ny), x, y in [0, 1)); values are rounded to the
+ * working precision.  PIC_E_CAPACITY if a tile overflows.  Synchronises. */
+int pic_set_particles(pic_sim *sim, int sp, long long n, const int *ix, const int *iy,
+                      const double *x, const double *y, const double *ux,
+                      const double *uy, const double *uz, void *stream);
+
+/* Number of particles of species sp.  Synchronises; returns < 0 on error. */
+long long pic_particle_count(pic_sim *sim, int sp, void *stream);
+
+/* Copy species sp to host arrays of capacity `cap` (tile by tile, in the
+ * order they are stored); *n_out receives the count.  PIC_E_ARG if cap is too
+ * small.  Synchronises. */
+int pic_get_particles(pic_sim *sim, int sp, long long cap, long long *n_out, int *ix,
+                      int *iy, double *x, double *y, double *ux, double *uy,
+                      double *uz, void *stream);
+
+/* Set / get the six field planes (6 * nx * ny doubles).  Synchronises. */
+int pic_set_fields(pic_sim *sim, const double *f6, void *stream);
+int pic_get_fields(pic_sim *sim, double *f6, void *stream);
+
+/* Current of the last step (3 * nx * ny doubles): filtered != 0 returns the
+ * current the field solver used, 0 the folded current before filtering.  With
+ * the moving window it is given in the window of the step that deposited it
+ * (before that step's shift, if any).  Synchronises. */
+int pic_get_current(pic_sim *sim, int filtered, double *j3, void *stream);
+
+/* Set the step counter and the number of window shifts done (to continue a
+ * run from a saved state).  Synchronises. */
+int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream);
+
+/* Per-kernel timing with HIP events recorded on `stream` around each launch
+ * of pic_deposit / pic_field_advance / pic_step (which then launch directly,
+ * not from the graph).  pic_timing(sim, 1) resets and starts, 0 stops.
+ * pic_timing_read fills ms[k] (summed milliseconds) and launches[k] for
+ * k < nk of: 0 push+deposit, 1 migrate, 2 fold, 3 filter, 4 Yee,
+ * 5 window/step bookkeeping.  Synchronises. */
+#define PIC_NK 6
+int pic_timing(pic_sim *sim, int enable, void *stream);
+int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void *stream);
+
+/* Geometry of the tiling: out[0] tile width, out[1] tile height, out[2]
+ * tiles along x, out[3] tiles along y, out[4] storage width in x, out[5]
+ * particle slots per tile of species 0, out[6] outbox slots per tile. */
+int pic_layout(const pic_sim *sim, long long *out, int n);
+
+const char *pic_strerror(int code);
+const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,851 @@
+// Host side of libpic: the C ABI declared in include/pic.h.  Validates the
+// configuration, lays the simulation out in the caller's device arena, moves
+// host state in and out, and enqueues the kernels of pic_kernels.hip on the
+// caller's stream (directly, or from a captured one-step HIP graph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_dev.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(PIC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Arena layout of one simulation.
+struct Layout {
+    int nxs, ntx, nty, ntiles;
+    int cap[MAX_SP];
+    int cap_out;
+    size_t rs;  // bytes of the working precision
+    size_t plane;  // elements of one storage plane
+    size_t off_state, off_F, off_J, off_Jf, off_rho, off_rho_f, off_rho_prev, off_g0, off_blk,
+        off_red, off_res;
+    size_t off_sp[MAX_SP];  // start of each species block
+    size_t sp_bytes[MAX_SP];
+    size_t total;
+};
+
+int layout(const pic_cfg *c, Layout *L)
+{
+    if (!c) return fail(PIC_E_ARG, "cfg is NULL");
+    if (c->nx < 2 || c->ny < 2 || c->nx > 32767 || c->ny > 32767)
+        return fail(PIC_E_ARG, "nx and ny must be in [2, 32767]");
+    if (!(c->lx > 0) || !(c->ly > 0) || !(c->dt > 0))
+        return fail(PIC_E_ARG, "lx, ly and dt must be positive");
+    if (c->ny % TY == 1) return fail(PIC_E_ARG, "ny % 16 == 1 would leave a one-cell tile");
+    if (!c->moving_window && c->nx % TX == 1)
+        return fail(PIC_E_ARG, "nx % 16 == 1 would leave a one-cell tile");
+    if (c->n_species < 0 || c->n_species > PIC_MAX_SPECIES)
+        return fail(PIC_E_ARG, "n_species must be in [0, 4]");
+    if (c->filter_passes < 0 || c->filter_passes + (c->filter_compensate ? 1 : 0) > MAX_FR ||
+        (c->filter_compensate && c->filter_passes == 0))
+        return fail(PIC_E_ARG, "filter: passes in [0, 4], compensator needs passes >= 1, "
+                               "passes + compensator <= 4");
+    const double dx = c->lx / c->nx, dy = c->ly / c->ny;
+    if (!(c->dt * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy)) < 1.0))
+        return fail(PIC_E_CFL, "dt violates the Courant limit dt < 1/sqrt(1/dx^2 + 1/dy^2)");
+    const double cf = c->capacity_factor > 0 ? c->capacity_factor : 3.0;
+    for (int s = 0; s < c->n_species; ++s) {
+        const pic_species_cfg &p = c->sp[s];
+        if (p.ppc_x < 1 || p.ppc_y < 1 || p.ppc_x * p.ppc_y > 1024)
+            return fail(PIC_E_ARG, "ppc_x, ppc_y must be >= 1 with ppc_x*ppc_y <= 1024");
+        if (p.q_over_m == 0.0 || !std::isfinite(p.q_over_m))
+            return fail(PIC_E_ARG, "q_over_m must be finite and non-zero");
+        if (p.density < 0) return fail(PIC_E_ARG, "density must be >= 0");
+    }
+    L->nxs = c->moving_window ? ((c->nx + TX + 2 + TX - 1) / TX) * TX : c->nx;
+    L->ntx = (L->nxs + TX - 1) / TX;
+    L->nty = (c->ny + TY - 1) / TY;
+    L->ntiles = L->ntx * L->nty;
+    L->rs = c->fp64 ? 8 : 4;
+    L->plane = (size_t)L->nxs * c->ny;
+    int maxcap = 64;
+    for (int s = 0; s < c->n_species; ++s) {
+        const double want = cf * c->sp[s].ppc_x * c->sp[s].ppc_y * TX * TY;
+        long long cap = ((long long)std::ceil(want) + 63) / 64 * 64;
+        cap = std::max<long long>(cap, 64);
+        if (cap > (1 << 26)) return fail(PIC_E_ARG, "capacity_factor too large");
+        L->cap[s] = (int)cap;
+        maxcap = std::max(maxcap, (int)cap);
+    }
+    L->cap_out = std::min(MAX_OUT, std::max(64, (maxcap / 8 + 63) / 64 * 64));
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L->off_state = take(sizeof(DevState));
+    L->off_F = take(12 * L->plane * L->rs);
+    L->off_J = take(3 * L->plane * L->rs);
+    L->off_Jf = take(3 * L->plane * L->rs);
+    L->off_rho = take(L->plane * L->rs);
+    L->off_rho_f = take(L->plane * L->rs);
+    L->off_rho_prev = take(L->plane * L->rs);
+    L->off_g0 = take(L->plane * 8);
+    L->off_blk = take((size_t)L->ntiles * 3 * BP * L->rs);
+    L->off_red = take(((size_t)NB_DIAG * 5 + (size_t)L->ntiles * MAX_SP) * 8);
+    L->off_res = take(N_RED * 8);
+    for (int s = 0; s < c->n_species; ++s) {
+        const size_t slots = (size_t)L->ntiles * L->cap[s];
+        const size_t obs = (size_t)L->ntiles * L->cap_out;
+        size_t b = 0;
+        b += align256(slots * 4) + 5 * align256(slots * L->rs);  // particles
+        b += align256((size_t)L->ntiles * 4);                     // count
+        b += 2 * align256(obs * 4) + 5 * align256(obs * L->rs);   // outbox + holes
+        b += align256((size_t)L->ntiles * 4);                     // outbox count
+        L->off_sp[s] = take(b);
+        L->sp_bytes[s] = b;
+    }
+    L->total = o;
+    return PIC_OK;
+}
+
+// Fill the device descriptor with arena pointers.
+template <typename R>
+void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
+{
+    std::memset((void *)d, 0, sizeof(*d));
+    d->nx = c->nx;
+    d->ny = c->ny;
+    d->nxs = L.nxs;
+    d->ntx = L.ntx;
+    d->nty = L.nty;
+    d->ntiles = L.ntiles;
+    d->window = c->moving_window ? 1 : 0;
+    d->nsp = c->n_species;
+    d->cap_out = L.cap_out;
+    d->npass = c->filter_passes;
+    d->compensate = c->filter_compensate ? 1 : 0;
+    d->dx_d = c->lx / c->nx;
+    d->dy_d = c->ly / c->ny;
+    d->dt_d = c->dt;
+    d->dx = (R)d->dx_d;
+    d->dy = (R)d->dy_d;
+    d->dt = (R)d->dt_d;
+    d->idx = (R)(1.0 / d->dx_d);
+    d->idy = (R)(1.0 / d->dy_d);
+    d->dt_dx = (R)(d->dt_d / d->dx_d);
+    d->dt_dy = (R)(d->dt_d / d->dy_d);
+    d->jxs = (R)(d->dx_d / d->dt_d);
+    d->jys = (R)(d->dy_d / d->dt_d);
+    d->key0 = (unsigned)(c->seed & 0xffffffffull);
+    d->key1 = (unsigned)(c->seed >> 32);
+    R *F = (R *)(a + L.off_F);
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 6; ++k) d->F[b][k] = F + (size_t)(b * 6 + k) * L.plane;
+    for (int k = 0; k < 3; ++k) {
+        d->J[k] = (R *)(a + L.off_J) + (size_t)k * L.plane;
+        d->Jf[k] = c->filter_passes > 0 ? (R *)(a + L.off_Jf) + (size_t)k * L.plane : d->J[k];
+    }
+    d->rho = (R *)(a + L.off_rho);
+    d->rho_f = (R *)(a + L.off_rho_f);
+    d->rho_prev = (R *)(a + L.off_rho_prev);
+    d->g0 = (double *)(a + L.off_g0);
+    d->blk = (R *)(a + L.off_blk);
+    d->red = (double *)(a + L.off_red);
+    d->res = (double *)(a + L.off_res);
+    d->st = (DevState *)(a + L.off_state);
+    for (int s = 0; s < c->n_species; ++s) {
+        const pic_species_cfg &p = c->sp[s];
+        SpDev<R> &P = d->sp[s];
+        const size_t slots = (size_t)L.ntiles * L.cap[s];
+        const size_t obs = (size_t)L.ntiles * L.cap_out;
+        char *q = a + L.off_sp[s];
+        auto next = [&](size_t bytes) {
+            char *r = q;
+            q += align256(bytes);
+            return r;
+        };
+        P.cell = (int *)next(slots * 4);
+        P.x = (R *)next(slots * L.rs);
+        P.y = (R *)next(slots * L.rs);
+        P.ux = (R *)next(slots * L.rs);
+        P.uy = (R *)next(slots * L.rs);
+        P.uz = (R *)next(slots * L.rs);
+        P.count = (int *)next((size_t)L.ntiles * 4);
+        P.ob_cell = (int *)next(obs * 4);
+        P.ob_hole = (int *)next(obs * 4);
+        P.ob_x = (R *)next(obs * L.rs);
+        P.ob_y = (R *)next(obs * L.rs);
+        P.ob_ux = (R *)next(obs * L.rs);
+        P.ob_uy = (R *)next(obs * L.rs);
+        P.ob_uz = (R *)next(obs * L.rs);
+        P.ob_count = (int *)next((size_t)L.ntiles * 4);
+        const double qp = (p.q_over_m < 0 ? -1.0 : 1.0) * p.density / (p.ppc_x * p.ppc_y);
+        P.qm = (R)p.q_over_m;
+        P.qp = (R)qp;
+        P.tau = (R)(0.5 * c->dt * p.q_over_m);
+        P.cap = L.cap[s];
+        P.ppc_x = p.ppc_x;
+        P.ppc_y = p.ppc_y;
+        P.density = p.density;
+        P.x_lo = p.x_lo;
+        P.x_hi = p.x_hi;
+        for (int k = 0; k < 3; ++k) {
+            P.uth[k] = p.uth[k];
+            P.ufl[k] = p.ufl[k];
+        }
+    }
+}
+
+// The initial laser of pic_laser_cfg at (x, y) (lab frame, t = 0).
+double laser_eperp(const pic_laser_cfg &l, double x, double y)
+{
+    const double d = x - l.x_center;
+    if (std::fabs(d) > 2.0 * l.fwhm) return 0.0;
+    const double g = std::exp(-2.0 * std::log(2.0) * d * d / (l.fwhm * l.fwhm));
+    const double z = x - l.focus, r = y - l.axis;
+    const double zr = 0.5 * l.omega0 * l.W0 * l.W0;
+    const double wz = l.W0 * std::sqrt(1.0 + (z / zr) * (z / zr));
+    const double curv = (z == 0.0) ? 0.0 : l.omega0 * r * r * z / (2.0 * (z * z + zr * zr));
+    return l.a0 * l.omega0 * g * std::sqrt(l.W0 / wz) * std::exp(-(r * r) / (wz * wz)) *
+           std::cos(l.omega0 * d + curv - 0.5 * std::atan(z / zr));
+}
+
+}  // namespace
+
+struct pic_sim {
+    pic_cfg cfg;
+    Layout L;
+    char *arena;
+    SimDev<float> df;
+    SimDev<double> dd;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    int ev_used = 0;
+    double ms[PIC_NK];
+    long long launches[PIC_NK];
+    // diagnostics
+    long long rho_prev_iter = -2;
+    DevState hs;  // host copy, valid after read_state
+};
+
+namespace {
+
+int read_state(pic_sim *s, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(&s->hs, s->arena + s->L.off_state, sizeof(DevState),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PIC_OK;
+}
+
+int write_state(pic_sim *s, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(s->arena + s->L.off_state, &s->hs, sizeof(DevState),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PIC_OK;
+}
+
+// Flush recorded event pairs into the per-kernel sums.
+int timing_flush(pic_sim *s)
+{
+    for (int i = 0; i < s->ev_used; ++i) {
+        HIPCHK(hipEventSynchronize(s->ev[2 * i + 1]));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
+        s->ms[s->ev_kind[i]] += ms;
+        s->launches[s->ev_kind[i]] += 1;
+    }
+    s->ev_used = 0;
+    return PIC_OK;
+}
+
+// Run `fn` (which enqueues one kernel class), bracketed by events if timing.
+template <typename Fn>
+int timed(pic_sim *s, int kind, hipStream_t st, Fn fn)
+{
+    if (!s->timing) {
+        hipError_t e = fn();
+        if (e != hipSuccess) return fail(PIC_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+        return PIC_OK;
+    }
+    if (s->ev_used >= 4096) {
+        int rc = timing_flush(s);
+        if (rc) return rc;
+    }
+    while ((int)s->ev.size() < 2 * (s->ev_used + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        s->ev.push_back(e);
+    }
+    if ((int)s->ev_kind.size() < s->ev_used + 1) s->ev_kind.resize(s->ev_used + 1);
+    HIPCHK(hipEventRecord(s->ev[2 * s->ev_used], st));
+    hipError_t e = fn();
+    if (e != hipSuccess) return fail(PIC_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+    HIPCHK(hipEventRecord(s->ev[2 * s->ev_used + 1], st));
+    s->ev_kind[s->ev_used] = kind;
+    s->ev_used += 1;
+    return PIC_OK;
+}
+
+template <typename R>
+int enqueue_deposit(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    int rc = timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
+    if (rc) return rc;
+    return timed(s, 1, st, [&] { return Launch<R>::migrate(d, st); });
+}
+
+template <typename R>
+int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    int rc = timed(s, 2, st, [&] { return Launch<R>::fold(d, 3, d.J[0], d.J[1], d.J[2], st); });
+    if (rc) return rc;
+    if (d.npass > 0) {
+        rc = timed(s, 3, st, [&] {
+            return Launch<R>::filter(d, 3, d.J[0], d.J[1], d.J[2], d.Jf[0], d.Jf[1], d.Jf[2], st);
+        });
+        if (rc) return rc;
+    }
+    rc = timed(s, 4, st, [&] { return Launch<R>::yee(d, st); });
+    if (rc) return rc;
+    rc = timed(s, 5, st, [&] { return Launch<R>::step_end(d, st); });
+    if (rc) return rc;
+    if (d.window) rc = timed(s, 5, st, [&] { return Launch<R>::window(d, st); });
+    return rc;
+}
+
+// Charge density of the current particles: rho, and F rho in rho_f.
+template <typename R>
+int enqueue_rho(const SimDev<R> &d, hipStream_t st)
+{
+    HIPCHK(Launch<R>::rho(d, st));
+    HIPCHK(Launch<R>::fold(d, 1, d.rho, nullptr, nullptr, st));
+    if (d.npass > 0)
+        HIPCHK(Launch<R>::filter(d, 1, d.rho, nullptr, nullptr, d.rho_f, nullptr, nullptr, st));
+    else
+        HIPCHK(Launch<R>::copy_plane(d.rho, d.rho_f, (long long)d.nxs * d.ny, st));
+    return PIC_OK;
+}
+
+template <typename R>
+int gauss_baseline(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    int rc = enqueue_rho(d, st);
+    if (rc) return rc;
+    HIPCHK(Launch<R>::g0(d, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s->rho_prev_iter = -2;
+    return PIC_OK;
+}
+
+template <typename R>
+int do_init(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    const pic_cfg &c = s->cfg;
+    const Layout &L = s->L;
+    HIPCHK(hipMemsetAsync(s->arena, 0, L.total, st));
+    if (c.laser.on) {
+        std::vector<R> h(L.plane * 6, R(0));
+        const pic_laser_cfg &l = c.laser;
+        const double cp = std::cos(l.pol_angle), sn = std::sin(l.pol_angle);
+        const double dx = d.dx_d, dy = d.dy_d;
+        for (int j = 0; j < c.ny; ++j)
+            for (int i = 0; i < c.nx; ++i) {
+                const size_t g = (size_t)i + (size_t)j * L.nxs;  // origin 0 at init
+                const double xi = i * dx, xh = (i + 0.5) * dx, yj = j * dy, yh = (j + 0.5) * dy;
+                h[1 * L.plane + g] = (R)(cp * laser_eperp(l, xi, yh));   // Ey (i, j+1/2)
+                h[2 * L.plane + g] = (R)(sn * laser_eperp(l, xi, yj));   // Ez (i, j)
+                h[4 * L.plane + g] = (R)(-sn * laser_eperp(l, xh, yj));  // By (i+1/2, j)
+                h[5 * L.plane + g] = (R)(cp * laser_eperp(l, xh, yh));   // Bz (i+1/2, j+1/2)
+            }
+        HIPCHK(hipMemcpyAsync(d.F[0][0], h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (c.load)
+        for (int sp = 0; sp < c.n_species; ++sp) HIPCHK(Launch<R>::load(d, sp, st));
+    int rc = gauss_baseline(s, d, st);
+    if (rc) return rc;
+    rc = read_state(s, st);
+    if (rc) return rc;
+    if (s->hs.err & ERR_CAPACITY)
+        return fail(PIC_E_CAPACITY, "initial load exceeds the tile capacity");
+    return PIC_OK;
+}
+
+template <typename R>
+int do_energy(pic_sim *s, const SimDev<R> &d, pic_diag *out, hipStream_t st)
+{
+    int rc = read_state(s, st);
+    if (rc) return rc;
+    const int has_prev = s->rho_prev_iter == s->hs.iter - 1;
+    rc = enqueue_rho(d, st);
+    if (rc) return rc;
+    HIPCHK(Launch<R>::diag(d, has_prev, st));
+    HIPCHK(Launch<R>::copy_plane(d.rho, d.rho_prev, (long long)d.nxs * d.ny, st));
+    double res[N_RED];
+    HIPCHK(hipMemcpyAsync(res, d.res, sizeof(res), hipMemcpyDeviceToHost, st));
+    std::vector<int> cnt((size_t)s->L.ntiles);
+    std::memset(out, 0, sizeof(*out));
+    double charge = 0;
+    for (int sp = 0; sp < d.nsp; ++sp) {
+        HIPCHK(hipMemcpyAsync(cnt.data(), d.sp[sp].count, cnt.size() * 4, hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+        long long n = 0;
+        for (int v : cnt) n += v;
+        out->n_particles[sp] = n;
+        const pic_species_cfg &p = s->cfg.sp[sp];
+        const double qp = (p.q_over_m < 0 ? -1.0 : 1.0) * p.density / (p.ppc_x * p.ppc_y);
+        charge += qp * (double)n * d.dx_d * d.dy_d;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    s->rho_prev_iter = s->hs.iter;
+    out->e_energy = res[0];
+    out->b_energy = res[1];
+    double ke = 0;
+    for (int sp = 0; sp < d.nsp; ++sp) {
+        out->ke[sp] = res[2 + sp];
+        ke += res[2 + sp];
+    }
+    out->total = res[0] + res[1] + ke;
+    out->charge = charge;
+    out->gauss_res_max = res[6];
+    out->cont_res_max = has_prev ? res[7] : -1.0;
+    out->rho_max = res[8];
+    out->step = s->hs.iter;
+    out->t = (double)s->hs.iter * d.dt_d;
+    out->nshift = s->hs.nshift;
+    out->status = (s->hs.err & ERR_CAPACITY) ? PIC_E_CAPACITY : PIC_OK;
+    return PIC_OK;
+}
+
+template <typename R>
+int do_set_particles(pic_sim *s, const SimDev<R> &d, int sp, long long n, const int *ix,
+                     const int *iy, const double *x, const double *y, const double *ux,
+                     const double *uy, const double *uz, hipStream_t st)
+{
+    const pic_cfg &c = s->cfg;
+    const Layout &L = s->L;
+    int rc = read_state(s, st);
+    if (rc) return rc;
+    const int origin = s->hs.origin;
+    std::vector<int> tile((size_t)n), cnt((size_t)L.ntiles, 0);
+    for (long long k = 0; k < n; ++k) {
+        if (ix[k] < 0 || ix[k] >= c.nx || iy[k] < 0 || iy[k] >= c.ny || !(x[k] >= 0.0) ||
+            !(x[k] < 1.0) || !(y[k] >= 0.0) || !(y[k] < 1.0) || !std::isfinite(ux[k]) ||
+            !std::isfinite(uy[k]) || !std::isfinite(uz[k]))
+            return fail(PIC_E_ARG, "particle " + std::to_string(k) + " out of range");
+        const int gx = c.moving_window ? (ix[k] + origin) % L.nxs : ix[k];
+        tile[k] = gx / TX + (iy[k] / TY) * L.ntx;
+        cnt[tile[k]] += 1;
+    }
+    for (int t = 0; t < L.ntiles; ++t)
+        if (cnt[t] > L.cap[sp]) return fail(PIC_E_CAPACITY, "a tile exceeds its particle slots");
+    // counting sort by tile, then one copy per array per non-empty tile
+    std::vector<long long> start((size_t)L.ntiles + 1, 0);
+    for (int t = 0; t < L.ntiles; ++t) start[t + 1] = start[t] + cnt[t];
+    std::vector<long long> fillp(start.begin(), start.end() - 1);
+    std::vector<int> hc((size_t)n);
+    std::vector<R> hx((size_t)n), hy((size_t)n), hux((size_t)n), huy((size_t)n), huz((size_t)n);
+    for (long long k = 0; k < n; ++k) {
+        const long long q = fillp[tile[k]]++;
+        const int gx = c.moving_window ? (ix[k] + origin) % L.nxs : ix[k];
+        R xr = (R)x[k], yr = (R)y[k];
+        if (xr >= R(1)) xr = std::nextafter(R(1), R(0));  // rounding must stay in [0, 1)
+        if (yr >= R(1)) yr = std::nextafter(R(1), R(0));
+        hc[q] = gx | (iy[k] << 16);
+        hx[q] = xr;
+        hy[q] = yr;
+        hux[q] = (R)ux[k];
+        huy[q] = (R)uy[k];
+        huz[q] = (R)uz[k];
+    }
+    const SpDev<R> &P = d.sp[sp];
+    for (int t = 0; t < L.ntiles; ++t) {
+        if (!cnt[t]) continue;
+        const size_t dst = (size_t)t * P.cap, src = (size_t)start[t], m = (size_t)cnt[t];
+        HIPCHK(hipMemcpyAsync(P.cell + dst, hc.data() + src, m * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(P.x + dst, hx.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(P.y + dst, hy.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(P.ux + dst, hux.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(P.uy + dst, huy.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(P.uz + dst, huz.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(P.count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return gauss_baseline(s, d, st);
+}
+
+template <typename R>
+int do_get_particles(pic_sim *s, const SimDev<R> &d, int sp, long long cap, long long *n_out,
+                     int *ix, int *iy, double *x, double *y, double *ux, double *uy, double *uz,
+                     hipStream_t st)
+{
+    const Layout &L = s->L;
+    int rc = read_state(s, st);
+    if (rc) return rc;
+    const SpDev<R> &P = d.sp[sp];
+    std::vector<int> cnt((size_t)L.ntiles);
+    HIPCHK(hipMemcpyAsync(cnt.data(), P.count, cnt.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    long long n = 0;
+    for (int v : cnt) n += v;
+    if (n_out) *n_out = n;
+    if (!ix) return PIC_OK;
+    if (n > cap) return fail(PIC_E_ARG, "output arrays too small");
+    std::vector<int> hc((size_t)n);
+    std::vector<R> hx((size_t)n), hy((size_t)n), hux((size_t)n), huy((size_t)n), huz((size_t)n);
+    long long q = 0;
+    for (int t = 0; t < L.ntiles; ++t) {
+        if (!cnt[t]) continue;
+        const size_t src = (size_t)t * P.cap, m = (size_t)cnt[t];
+        HIPCHK(hipMemcpyAsync(hc.data() + q, P.cell + src, m * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hx.data() + q, P.x + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hy.data() + q, P.y + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hux.data() + q, P.ux + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(huy.data() + q, P.uy + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(huz.data() + q, P.uz + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
+        q += (long long)m;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    const int origin = s->hs.origin;
+    for (long long k = 0; k < n; ++k) {
+        const int gx = hc[k] & 0xffff;
+        ix[k] = s->cfg.moving_window ? (gx - origin + L.nxs) % L.nxs : gx;
+        iy[k] = hc[k] >> 16;
+        x[k] = hx[k];
+        y[k] = hy[k];
+        ux[k] = hux[k];
+        uy[k] = huy[k];
+        uz[k] = huz[k];
+    }
+    return PIC_OK;
+}
+
+// Host (ny, nx) window planes <-> device storage planes.
+// lag = 1 maps with the window origin before the last step's shift (the
+// current of a step lives in the window it was deposited in).
+template <typename R>
+int do_planes(pic_sim *s, R *const *dev, int np, double *host, bool to_dev, hipStream_t st,
+              int lag = 0)
+{
+    const Layout &L = s->L;
+    const pic_cfg &c = s->cfg;
+    int rc = read_state(s, st);
+    if (rc) return rc;
+    const int origin = (s->hs.origin - (lag ? s->hs.shift : 0) + L.nxs) % L.nxs;
+    std::vector<R> h(L.plane);
+    const size_t hp = (size_t)c.nx * c.ny;
+    for (int k = 0; k < np; ++k) {
+        if (to_dev) {
+            std::fill(h.begin(), h.end(), R(0));
+            for (int j = 0; j < c.ny; ++j)
+                for (int i = 0; i < c.nx; ++i) {
+                    const int gx = c.moving_window ? (i + origin) % L.nxs : i;
+                    h[(size_t)gx + (size_t)j * L.nxs] = (R)host[k * hp + (size_t)j * c.nx + i];
+                }
+            HIPCHK(hipMemcpyAsync(dev[k], h.data(), L.plane * sizeof(R), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        } else {
+            HIPCHK(hipMemcpyAsync(h.data(), dev[k], L.plane * sizeof(R), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int j = 0; j < c.ny; ++j)
+                for (int i = 0; i < c.nx; ++i) {
+                    const int gx = c.moving_window ? (i + origin) % L.nxs : i;
+                    host[k * hp + (size_t)j * c.nx + i] = (double)h[(size_t)gx + (size_t)j * L.nxs];
+                }
+        }
+    }
+    return PIC_OK;
+}
+
+template <typename R>
+int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
+{
+    if (s->timing) {
+        for (int n = 0; n < nsteps; ++n) {
+            int rc = enqueue_deposit(s, d, st);
+            if (rc) return rc;
+            rc = enqueue_field_advance(s, d, st);
+            if (rc) return rc;
+        }
+        return PIC_OK;
+    }
+    if (!s->gexec) {
+        if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+        int rc = enqueue_deposit(s, d, s->cap_stream);
+        if (!rc) rc = enqueue_field_advance(s, d, s->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (rc) return rc;
+        if (e != hipSuccess)
+            return fail(PIC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        s->graph = g;
+        HIPCHK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+    }
+    for (int n = 0; n < nsteps; ++n) HIPCHK(hipGraphLaunch(s->gexec, st));
+    return PIC_OK;
+}
+
+}  // namespace
+
+#define DISPATCH(sim, call_f, call_d) ((sim)->cfg.fp64 ? (call_d) : (call_f))
+
+extern "C" {
+
+size_t pic_mem_bytes(const pic_cfg *cfg)
+{
+    Layout L;
+    if (layout(cfg, &L) != PIC_OK) return 0;
+    return L.total;
+}
+
+int pic_init(const pic_cfg *cfg, void *arena, size_t arena_bytes, void *stream, pic_sim **out)
+{
+    if (!out) return fail(PIC_E_ARG, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    int rc = layout(cfg, &L);
+    if (rc) return rc;
+    if (!arena) return fail(PIC_E_ARG, "arena is NULL");
+    if (((uintptr_t)arena) & 255) return fail(PIC_E_ARG, "arena must be 256-byte aligned");
+    if (arena_bytes < L.total)
+        return fail(PIC_E_NOMEM, "arena holds " + std::to_string(arena_bytes) + " bytes, needs " +
+                                     std::to_string(L.total));
+    pic_sim *s = new pic_sim();
+    s->cfg = *cfg;
+    s->L = L;
+    s->arena = (char *)arena;
+    std::memset(s->ms, 0, sizeof(s->ms));
+    std::memset(s->launches, 0, sizeof(s->launches));
+    hipStream_t st = (hipStream_t)stream;
+    if (cfg->fp64) {
+        describe(cfg, L, s->arena, &s->dd);
+        rc = do_init(s, s->dd, st);
+    } else {
+        describe(cfg, L, s->arena, &s->df);
+        rc = do_init(s, s->df, st);
+    }
+    if (rc) {
+        pic_free(s);
+        return rc;
+    }
+    *out = s;
+    return PIC_OK;
+}
+
+int pic_deposit(pic_sim *sim, void *stream)
+{
+    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim, enqueue_deposit(sim, sim->df, st), enqueue_deposit(sim, sim->dd, st));
+}
+
+int pic_field_advance(pic_sim *sim, void *stream)
+{
+    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim, enqueue_field_advance(sim, sim->df, st),
+                    enqueue_field_advance(sim, sim->dd, st));
+}
+
+int pic_step(pic_sim *sim, int nsteps, void *stream)
+{
+    if (!sim || nsteps < 0) return fail(PIC_E_ARG, "bad sim or nsteps");
+    if (nsteps == 0) return PIC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim, do_step(sim, sim->df, nsteps, st), do_step(sim, sim->dd, nsteps, st));
+}
+
+int pic_energy(pic_sim *sim, pic_diag *out, void *stream)
+{
+    if (!sim || !out) return fail(PIC_E_ARG, "sim or out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim, do_energy(sim, sim->df, out, st), do_energy(sim, sim->dd, out, st));
+}
+
+int pic_status(pic_sim *sim, void *stream)
+{
+    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+    int rc = read_state(sim, (hipStream_t)stream);
+    if (rc) return rc;
+    if (sim->hs.err & ERR_CAPACITY)
+        return fail(PIC_E_CAPACITY, "a tile or outbox ran out of particle slots");
+    return PIC_OK;
+}
+
+int pic_free(pic_sim *sim)
+{
+    if (!sim) return PIC_OK;
+    if (sim->gexec) (void)hipGraphExecDestroy(sim->gexec);
+    if (sim->graph) (void)hipGraphDestroy(sim->graph);
+    if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
+    for (hipEvent_t e : sim->ev) (void)hipEventDestroy(e);
+    delete sim;
+    return PIC_OK;
+}
+
+int pic_set_particles(pic_sim *sim, int sp, long long n, const int *ix, const int *iy,
+                      const double *x, const double *y, const double *ux, const double *uy,
+                      const double *uz, void *stream)
+{
+    if (!sim || sp < 0 || sp >= sim->cfg.n_species || n < 0)
+        return fail(PIC_E_ARG, "bad sim, species or count");
+    if (n > 0 && (!ix || !iy || !x || !y || !ux || !uy || !uz))
+        return fail(PIC_E_ARG, "NULL particle array");
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim,
+                    do_set_particles(sim, sim->df, sp, n, ix, iy, x, y, ux, uy, uz, st),
+                    do_set_particles(sim, sim->dd, sp, n, ix, iy, x, y, ux, uy, uz, st));
+}
+
+long long pic_particle_count(pic_sim *sim, int sp, void *stream)
+{
+    if (!sim || sp < 0 || sp >= sim->cfg.n_species) return fail(PIC_E_ARG, "bad sim or species");
+    long long n = 0;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = DISPATCH(sim,
+                      do_get_particles(sim, sim->df, sp, 0, &n, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, nullptr, nullptr, st),
+                      do_get_particles(sim, sim->dd, sp, 0, &n, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, nullptr, nullptr, st));
+    return rc ? rc : n;
+}
+
+int pic_get_particles(pic_sim *sim, int sp, long long cap, long long *n_out, int *ix, int *iy,
+                      double *x, double *y, double *ux, double *uy, double *uz, void *stream)
+{
+    if (!sim || sp < 0 || sp >= sim->cfg.n_species || !ix || !iy || !x || !y || !ux || !uy ||
+        !uz)
+        return fail(PIC_E_ARG, "bad sim, species or NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim,
+                    do_get_particles(sim, sim->df, sp, cap, n_out, ix, iy, x, y, ux, uy, uz, st),
+                    do_get_particles(sim, sim->dd, sp, cap, n_out, ix, iy, x, y, ux, uy, uz, st));
+}
+
+int pic_set_fields(pic_sim *sim, const double *f6, void *stream)
+{
+    if (!sim || !f6) return fail(PIC_E_ARG, "bad sim or NULL planes");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = read_state(sim, st);
+    if (rc) return rc;
+    const int par = sim->hs.parity;
+    if (sim->cfg.fp64) {
+        rc = do_planes(sim, sim->dd.F[par], 6, (double *)f6, true, st);
+        if (!rc) rc = gauss_baseline(sim, sim->dd, st);
+    } else {
+        rc = do_planes(sim, sim->df.F[par], 6, (double *)f6, true, st);
+        if (!rc) rc = gauss_baseline(sim, sim->df, st);
+    }
+    return rc;
+}
+
+int pic_get_fields(pic_sim *sim, double *f6, void *stream)
+{
+    if (!sim || !f6) return fail(PIC_E_ARG, "bad sim or NULL planes");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = read_state(sim, st);
+    if (rc) return rc;
+    const int par = sim->hs.parity;
+    return DISPATCH(sim, do_planes(sim, sim->df.F[par], 6, f6, false, st),
+                    do_planes(sim, sim->dd.F[par], 6, f6, false, st));
+}
+
+int pic_get_current(pic_sim *sim, int filtered, double *j3, void *stream)
+{
+    if (!sim || !j3) return fail(PIC_E_ARG, "bad sim or NULL planes");
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(sim, do_planes(sim, filtered ? sim->df.Jf : sim->df.J, 3, j3, false, st, 1),
+                    do_planes(sim, filtered ? sim->dd.Jf : sim->dd.J, 3, j3, false, st, 1));
+}
+
+int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream)
+{
+    if (!sim || iter < 0 || nshift < 0) return fail(PIC_E_ARG, "bad sim, iter or nshift");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = read_state(sim, st);
+    if (rc) return rc;
+    sim->hs.iter = iter;
+    sim->hs.nshift = nshift;
+    sim->rho_prev_iter = -2;
+    return write_state(sim, st);
+}
+
+int pic_timing(pic_sim *sim, int enable, void *stream)
+{
+    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    sim->timing = enable != 0;
+    sim->ev_used = 0;
+    if (enable) {
+        std::memset(sim->ms, 0, sizeof(sim->ms));
+        std::memset(sim->launches, 0, sizeof(sim->launches));
+    }
+    return PIC_OK;
+}
+
+int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void *stream)
+{
+    if (!sim || nk < 0) return fail(PIC_E_ARG, "bad sim or nk");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    int rc = timing_flush(sim);
+    if (rc) return rc;
+    for (int k = 0; k < nk && k < PIC_NK; ++k) {
+        if (ms) ms[k] = sim->ms[k];
+        if (launches) launches[k] = sim->launches[k];
+    }
+    return PIC_OK;
+}
+
+int pic_layout(const pic_sim *sim, long long *out, int n)
+{
+    if (!sim || !out) return fail(PIC_E_ARG, "bad sim or out");
+    const long long v[7] = {TX, TY, sim->L.ntx, sim->L.nty, sim->L.nxs,
+                            sim->cfg.n_species ? sim->L.cap[0] : 0, sim->L.cap_out};
+    for (int k = 0; k < n && k < 7; ++k) out[k] = v[k];
+    return PIC_OK;
+}
+
+const char *pic_strerror(int code)
+{
+    switch (code) {
+    case PIC_OK: return "ok";
+    case PIC_E_ARG: return "invalid argument";
+    case PIC_E_CFL: return "timestep violates the Courant limit";
+    case PIC_E_NOMEM: return "arena too small";
+    case PIC_E_CAPACITY: return "particle capacity exceeded";
+    case PIC_E_HIP: return "HIP runtime error";
+    case PIC_E_STATE: return "invalid state";
+    default: return "unknown error";
+    }
+}
+
+const char *pic_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

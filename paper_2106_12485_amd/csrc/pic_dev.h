@@ -1,0 +1,140 @@
+// Device-side layout of one simulation and the helpers shared by the kernels.
+//
+// Grid: nx x ny cells.  Storage is row-major with x fastest; with the moving
+// window the x axis is a ring of nxs >= nx + TX + 2 columns in which window
+// column w lives at storage column (origin + w) mod nxs and the other
+// nxs - nx columns (the "gap") are held at zero.  The gap is wider than a tile
+// plus its guard cells, so no tile's halo ever sees both window edges.
+//
+// Tiles: TX x TY cells (the paper's regions with ghost cells, Sec. 3.2).  A
+// tile owns a fixed segment of `cap` particle slots per species, of which the
+// first count[t] are live.  Fields and current are staged per tile in LDS on
+// local cells [-1, TX+2) x [-1, TY+2): one guard cell below and two above,
+// which is the reach of bilinear interpolation of the staggered components
+// (one cell each way) and of the charge-conserving deposit of a particle that
+// moves at most one cell per step (two cells up).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int TX = 16;
+constexpr int TY = 16;
+constexpr int PX = TX + 3;          // LDS row pitch of a tile block
+constexpr int PY = TY + 3;
+constexpr int BP = PX * PY;         // cells of a tile block
+constexpr int NT = 256;             // threads per block (4 wavefronts)
+constexpr int MAX_SP = 4;
+constexpr int MAX_OUT = 4096;       // outbox slots per tile and species
+constexpr int MAX_FR = 4;           // largest filter halo (passes + compensator)
+constexpr int QX = TX + 2 * MAX_FR; // LDS pitch of the filter block
+constexpr int QY = TY + 2 * MAX_FR;
+constexpr int ERR_CAPACITY = 1;
+constexpr int N_RED = 16;           // result slots of the diagnostic reduction
+constexpr int NB_DIAG = 512;        // blocks of the grid-stride diagnostic kernels
+
+// Mutable per-simulation state read by every kernel of a step, so that one
+// captured step graph can be replayed.
+struct DevState {
+    long long iter;   // completed steps
+    int parity;       // field buffer holding E^n, B^n
+    int origin;       // storage column of window column 0
+    int nshift;       // window shifts done
+    int shift;        // 1 if the last step shifted the window
+    int err;          // ERR_* bits
+    int pad;
+};
+
+template <typename R>
+struct SpDev {
+    int *cell;        // packed storage cell: ix | iy << 16 (-1 = removed)
+    R *x, *y, *ux, *uy, *uz;
+    int *count;       // live particles per tile
+    int *ob_cell;     // outbox of leavers: ntiles x cap_out
+    R *ob_x, *ob_y, *ob_ux, *ob_uy, *ob_uz;
+    int *ob_hole;     // slot each leaver left behind in its tile
+    int *ob_count;    // leavers (= holes) per tile
+    R qm, qp, tau;    // q/m, charge per particle, (dt/2)(q/m)
+    int cap;          // slots per tile
+    int ppc_x, ppc_y;
+    double density, x_lo, x_hi;
+    double uth[3], ufl[3];
+};
+
+template <typename R>
+struct SimDev {
+    int nx, ny, nxs;
+    int ntx, nty, ntiles;
+    int window, nsp, cap_out;
+    int npass, compensate;
+    R dx, dy, dt;
+    R idx, idy;       // 1/dx, 1/dy
+    R dt_dx, dt_dy;   // dt/dx, dt/dy
+    R jxs, jys;       // dx/dt, dy/dt
+    double dx_d, dy_d, dt_d;
+    unsigned key0, key1;
+    R *F[2][6];       // ping-pong Ex Ey Ez Bx By Bz
+    R *J[3];          // folded current of the last step
+    R *Jf[3];         // filtered current (aliases J without a filter)
+    R *blk;           // per-tile current blocks: ntiles x 3 x BP
+    R *rho, *rho_f, *rho_prev;
+    double *g0;       // div E^0 - F rho^0
+    double *red;      // reduction partials
+    double *res;      // N_RED reduced results
+    DevState *st;
+    SpDev<R> sp[MAX_SP];
+};
+
+__device__ __forceinline__ int wrapi(int a, int n)
+{
+    a += (a < 0) ? n : 0;
+    a -= (a >= n) ? n : 0;
+    return a;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run
+// of tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_add(R *p, R v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int pack_cell(int ix, int iy) { return ix | (iy << 16); }
+__device__ __forceinline__ int cell_x(int c) { return c & 0xffff; }
+__device__ __forceinline__ int cell_y(int c) { return c >> 16; }
+
+// window coordinate of storage column gx (>= nx means the gap)
+__device__ __forceinline__ int window_col(int gx, int origin, int nxs)
+{
+    int w = gx - origin;
+    return w < 0 ? w + nxs : w;
+}
+
+// Launchers (defined in pic_kernels.hip for R = float and double).
+template <typename R> struct Launch {
+    static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
+    static hipError_t migrate(const SimDev<R> &d, hipStream_t s);
+    static hipError_t fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s);
+    static hipError_t filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
+                             const R *i2, R *o0, R *o1, R *o2, hipStream_t s);
+    static hipError_t yee(const SimDev<R> &d, hipStream_t s);
+    static hipError_t step_end(const SimDev<R> &d, hipStream_t s);
+    static hipError_t window(const SimDev<R> &d, hipStream_t s);
+    static hipError_t load(const SimDev<R> &d, int sp, hipStream_t s);
+    static hipError_t rho(const SimDev<R> &d, hipStream_t s);
+    static hipError_t g0(const SimDev<R> &d, hipStream_t s);
+    static hipError_t diag(const SimDev<R> &d, int has_prev, hipStream_t s);
+    static hipError_t copy_plane(const R *src, R *dst, long long n, hipStream_t s);
+};
+
+}  // namespace pic

@@ -1,0 +1,1124 @@
+// HIP kernels for gfx950 of one 2D EM-PIC timestep (paper Sec. 2.2, Fig. 1):
+// stage 1 interpolation, stage 2 Boris push, stage 3 charge-conserving
+// deposit (+ filter), stage 4 Yee FDTD; plus the tile hand-off of particles
+// (the paper's particle transfer between regions, Sec. 3.2) and the moving
+// window and loading of Sec. 4.1.  Every kernel is a template over the working
+// precision R (float for the production path, double for the FP64 path).
+#include "pic_dev.h"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R lerp2(const R *f, int i, int j, R wx, R wy)
+{
+    // bilinear value on the corner (i, j) of an LDS tile block, i, j >= -1
+    const R *p = f + (i + 1) + (j + 1) * PX;
+    const R a = p[0] + wx * (p[1] - p[0]);
+    const R b = p[PX] + wx * (p[PX + 1] - p[PX]);
+    return a + wy * (b - a);
+}
+
+// Inclusive-exclusive block scan of a predicate: returns the exclusive rank of
+// this thread's `pred` among the block and writes the block total to *total.
+__device__ int block_rank(bool pred, int *s_w, int *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(pred);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_w[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+        const int c = s_w[k];
+        off += (k < wv) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + before;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box with
+// multipliers 0xD2511F53, 0xCD9E8D57 and key increments 0x9E3779B9, 0xBB67AE85.
+__device__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t a = c[0], b = c[2];
+        const uint32_t lo0 = 0xD2511F53u * a, hi0 = __umulhi(0xD2511F53u, a);
+        const uint32_t lo1 = 0xCD9E8D57u * b, hi1 = __umulhi(0xCD9E8D57u, b);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Maxwellian momentum of the particle loaded at (lab cell x, cell y,
+// sub-position) of species s: Box-Muller in double on both word pairs.
+template <typename R>
+__device__ void maxwellian(const SpDev<R> &P, uint32_t key0, uint32_t key1, uint32_t ilab,
+                           uint32_t j, uint32_t sub, uint32_t s, R *u)
+{
+    uint32_t c[4] = {ilab, j, sub, s};
+    philox4x32_10(c, key0, key1);
+    const double two32 = 4294967296.0;
+    const double r0 = sqrt(-2.0 * log(((double)c[0] + 1.0) / two32));
+    const double a0 = 2.0 * M_PI * ((double)c[1] / two32);
+    const double r1 = sqrt(-2.0 * log(((double)c[2] + 1.0) / two32));
+    const double a1 = 2.0 * M_PI * ((double)c[3] / two32);
+    const double n0 = r0 * cos(a0), n1 = r0 * sin(a0), n2 = r1 * cos(a1);
+    u[0] = (R)(P.ufl[0] + P.uth[0] * n0);
+    u[1] = (R)(P.ufl[1] + P.uth[1] * n1);
+    u[2] = (R)(P.ufl[2] + P.uth[2] * n2);
+}
+
+// ---------------------------------------------------------------------------
+// stage 3: Villasenor-Buneman deposit of one straight segment that lies in
+// the cell (lx+cx, ly+cy) of the tile block.  The segment is the part
+// t in [ta, tb] of the step of a particle starting at offset (x, y) of cell
+// (lx, ly) with displacement (ddx, ddy) cells.  Its x extent is (tb-ta)*ddx,
+// taken from the displacement rather than from differences of positions so
+// that slow particles keep full relative accuracy in FP32.
+// Jz uses the exact time average of the bilinear node weight along the
+// segment: weight at the midpoint +- (extent_x * extent_y)/12.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void deposit_segment(R *sj, int lx, int ly, R x, R y, R ddx, R ddy,
+                                                R vz, R qjx, R qjy, R qp, R ta, R tb, int cx,
+                                                int cy)
+{
+    const R f = tb - ta;
+    const R tm = R(0.5) * (ta + tb);
+    const R xm = x + tm * ddx - (R)cx;
+    const R ym = y + tm * ddy - (R)cy;
+    const R sx = f * ddx, sy = f * ddy;
+    const R ax = qjx * sx, ay = qjy * sy;
+    const R az = qp * vz * f, corr = sx * sy * R(1.0 / 12.0);
+    const int k = (lx + cx + 1) + (ly + cy + 1) * PX;
+    R *jx = sj, *jy = sj + BP, *jz = sj + 2 * BP;
+    lds_add(jx + k, ax * (R(1) - ym));
+    lds_add(jx + k + PX, ax * ym);
+    lds_add(jy + k, ay * (R(1) - xm));
+    lds_add(jy + k + 1, ay * xm);
+    lds_add(jz + k, az * ((R(1) - xm) * (R(1) - ym) + corr));
+    lds_add(jz + k + 1, az * (xm * (R(1) - ym) - corr));
+    lds_add(jz + k + PX, az * ((R(1) - xm) * ym - corr));
+    lds_add(jz + k + PX + 1, az * (xm * ym + corr));
+}
+
+// Split the straight move at the cell boundaries it crosses (at most one per
+// axis since |ddx|, |ddy| < 1), in the order the path crosses them.
+template <typename R>
+__device__ __forceinline__ void deposit_move(R *sj, int lx, int ly, R x, R y, R ddx, R ddy,
+                                             R vz, R qjx, R qjy, R qp)
+{
+    const R x1 = x + ddx, y1 = y + ddy;
+    const int di = (x1 >= R(1)) - (x1 < R(0));
+    const int dj = (y1 >= R(1)) - (y1 < R(0));
+    R tx = R(1), ty = R(1);
+    if (di) tx = fmin(((di > 0 ? R(1) : R(0)) - x) / ddx, R(1));
+    if (dj) ty = fmin(((dj > 0 ? R(1) : R(0)) - y) / ddy, R(1));
+    const bool xfirst = tx <= ty;
+    const R t1 = xfirst ? tx : ty, t2 = xfirst ? ty : tx;
+    if (t1 > R(0))
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, R(0), t1, 0, 0);
+    if (t2 > t1)
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t1, t2, xfirst ? di : 0,
+                        xfirst ? 0 : dj);
+    if (R(1) > t2)
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t2, R(1), di, dj);
+}
+
+// Load the six field planes of buffer `par` on the tile block (periodic wrap
+// in storage; gap columns hold zeros) and clear the current block.
+template <typename R>
+__device__ __forceinline__ void load_tile_fields(const SimDev<R> &d, int par, int x0, int y0,
+                                                 int w, int h, R *sf, R *sj)
+{
+    for (int k = threadIdx.x; k < BP; k += NT) {
+        const int lx = k % PX - 1, ly = k / PX - 1;
+        const bool in = lx < w + 2 && ly < h + 2;
+        const int gx = wrapi(x0 + lx, d.nxs), gy = wrapi(y0 + ly, d.ny);
+        const size_t g = in ? (size_t)gx + (size_t)gy * d.nxs : 0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const R *Fc = par ? d.F[1][c] : d.F[0][c];
+            sf[c * BP + k] = in ? Fc[g] : R(0);
+        }
+        if (sj) {
+            sj[k] = R(0);
+            sj[BP + k] = R(0);
+            sj[2 * BP + k] = R(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rows a1-a3 (+ the leaver test of a4): one block per tile
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
+{
+    __shared__ R sf[6 * BP];
+    __shared__ R sj[3 * BP];
+    __shared__ int s_nout;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    const int par = d.st->parity;
+    const int origin = d.st->origin;
+    load_tile_fields(d, par, x0, y0, w, h, sf, sj);
+    if (threadIdx.x == 0) s_nout = 0;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    for (int s = 0; s < d.nsp; ++s) {
+        const SpDev<R> &P = d.sp[s];
+        const int n = P.count[t];
+        const size_t base = (size_t)t * P.cap;
+        const R qjx = P.qp * d.jxs, qjy = P.qp * d.jys;
+        for (int p0 = 0; p0 < n; p0 += NT) {
+            const int p = p0 + threadIdx.x;
+            bool leave = false, dead = false;
+            int ncell = 0;
+            R xn = 0, yn = 0, ux = 0, uy = 0, uz = 0;
+            if (p < n) {
+                const size_t q = base + p;
+                const int cell = P.cell[q];
+                const R x = P.x[q], y = P.y[q];
+                ux = P.ux[q];
+                uy = P.uy[q];
+                uz = P.uz[q];
+                const int ix = cell_x(cell), iy = cell_y(cell);
+                const int lx = ix - x0, ly = iy - y0;
+                // stage 1: each component from its own staggered grid
+                const bool lox = x < R(0.5), loy = y < R(0.5);
+                const int ixh = lx - (lox ? 1 : 0), iyh = ly - (loy ? 1 : 0);
+                const R wxh = x + (lox ? R(0.5) : R(-0.5));
+                const R wyh = y + (loy ? R(0.5) : R(-0.5));
+                const R ex = lerp2(sf, ixh, ly, wxh, y);
+                const R ey = lerp2(sf + BP, lx, iyh, x, wyh);
+                const R ez = lerp2(sf + 2 * BP, lx, ly, x, y);
+                const R bx = lerp2(sf + 3 * BP, lx, iyh, x, wyh);
+                const R by = lerp2(sf + 4 * BP, ixh, ly, wxh, y);
+                const R bz = lerp2(sf + 5 * BP, ixh, iyh, wxh, wyh);
+                // stage 2: relativistic Boris
+                const R tau = P.tau;
+                const R umx = ux + tau * ex, umy = uy + tau * ey, umz = uz + tau * ez;
+                const R ig = R(1) / sqrt(R(1) + umx * umx + umy * umy + umz * umz);
+                const R tvx = tau * bx * ig, tvy = tau * by * ig, tvz = tau * bz * ig;
+                const R upx = umx + (umy * tvz - umz * tvy);
+                const R upy = umy + (umz * tvx - umx * tvz);
+                const R upz = umz + (umx * tvy - umy * tvx);
+                const R fs = R(2) / (R(1) + tvx * tvx + tvy * tvy + tvz * tvz);
+                const R svx = fs * tvx, svy = fs * tvy, svz = fs * tvz;
+                ux = umx + (upy * svz - upz * svy) + tau * ex;
+                uy = umy + (upz * svx - upx * svz) + tau * ey;
+                uz = umz + (upx * svy - upy * svx) + tau * ez;
+                // move and stage 3
+                const R ig2 = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+                const R ddx = d.dt_dx * ux * ig2, ddy = d.dt_dy * uy * ig2;
+                deposit_move(sj, lx, ly, x, y, ddx, ddy, uz * ig2, qjx, qjy, P.qp);
+                xn = x + ddx;
+                yn = y + ddy;
+                int di = (xn >= R(1)) - (xn < R(0));
+                int dj = (yn >= R(1)) - (yn < R(0));
+                xn -= (R)di;
+                yn -= (R)dj;
+                // x + ddx in (-2^-25, 0) rounds to exactly 1 after adding 1
+                if (xn >= R(1)) { xn -= R(1); di += 1; }
+                if (yn >= R(1)) { yn -= R(1); dj += 1; }
+                const int nix = wrapi(ix + di, d.nxs), niy = wrapi(iy + dj, d.ny);
+                if (d.window) dead = window_col(nix, origin, d.nxs) >= d.nx;
+                ncell = pack_cell(nix, niy);
+                leave = dead || (nix / TX + (niy / TY) * d.ntx) != t;
+                if (!leave) {
+                    P.cell[q] = ncell;
+                    P.x[q] = xn;
+                    P.y[q] = yn;
+                    P.ux[q] = ux;
+                    P.uy[q] = uy;
+                    P.uz[q] = uz;
+                }
+            }
+            // row a4: wavefront ballot + prefix count gives each leaver its
+            // outbox slot; one LDS atomic per wavefront
+            const unsigned long long m = __ballot(leave);
+            if (m) {
+                int off = 0;
+                if (lane == 0) off = atomicAdd(&s_nout, (int)__popcll(m));
+                off = __shfl(off, 0);
+                if (leave) {
+                    const int slot = off + (int)__popcll(m & ((1ull << lane) - 1ull));
+                    if (slot < d.cap_out) {
+                        const size_t o = (size_t)t * d.cap_out + slot;
+                        P.ob_hole[o] = p;
+                        P.ob_cell[o] = dead ? -1 : ncell;
+                        P.ob_x[o] = xn;
+                        P.ob_y[o] = yn;
+                        P.ob_ux[o] = ux;
+                        P.ob_uy[o] = uy;
+                        P.ob_uz[o] = uz;
+                    } else {
+                        atomicOr(&d.st->err, ERR_CAPACITY);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            P.ob_count[t] = min(s_nout, d.cap_out);
+            s_nout = 0;
+        }
+        __syncthreads();
+    }
+    // one flush of the tile's current block per step
+    R *out = d.blk + (size_t)t * 3 * BP;
+    for (int k = threadIdx.x; k < 3 * BP; k += NT) out[k] = sj[k];
+}
+
+// ---------------------------------------------------------------------------
+// row a4: hand-off of leavers to the tile that now holds them.  One block per
+// (tile, species).  Incoming particles fill the holes below the new count
+// first, then append; if fewer arrive than left, live particles from the tail
+// move into the remaining holes.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(NT) void k_migrate(SimDev<R> d)
+{
+    __shared__ int s_low[MAX_OUT];
+    __shared__ unsigned s_bits[MAX_OUT / 32];
+    __shared__ int s_nb[8];
+    __shared__ int s_nnb, s_in, s_nlow, s_ctr, s_ctr2;
+    const int t = blockIdx.x, s = blockIdx.y;
+    const SpDev<R> &P = d.sp[s];
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    if (threadIdx.x == 0) {
+        int nn = 0;
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (!ox && !oy) continue;
+                const int nb = wrapi(tx + ox, d.ntx) + wrapi(ty + oy, d.nty) * d.ntx;
+                bool dup = nb == t;
+                for (int k = 0; k < nn; ++k) dup |= s_nb[k] == nb;
+                if (!dup) s_nb[nn++] = nb;
+            }
+        s_nnb = nn;
+        s_in = 0;
+        s_nlow = 0;
+        s_ctr = 0;
+        s_ctr2 = 0;
+    }
+    for (int k = threadIdx.x; k < MAX_OUT / 32; k += NT) s_bits[k] = 0u;
+    __syncthreads();
+    const int cap_out = d.cap_out;
+    // incoming count
+    int mine = 0;
+    for (int q = 0; q < s_nnb; ++q) {
+        const int nb = s_nb[q], no = P.ob_count[nb];
+        for (int k = threadIdx.x; k < no; k += NT) {
+            const int c = P.ob_cell[(size_t)nb * cap_out + k];
+            mine += (c >= 0 && cell_x(c) / TX + (cell_y(c) / TY) * d.ntx == t) ? 1 : 0;
+        }
+    }
+    if (mine) atomicAdd(&s_in, mine);
+    __syncthreads();
+    const int n_old = P.count[t], H = P.ob_count[t];
+    int I = s_in;
+    int n_new = n_old - H + I;
+    if (n_new > P.cap) {
+        I = P.cap - (n_old - H);
+        n_new = P.cap;
+        if (threadIdx.x == 0) atomicOr(&d.st->err, ERR_CAPACITY);
+    }
+    // holes below the new count are targets; holes at or above it are skipped
+    for (int k = threadIdx.x; k < H; k += NT) {
+        const int hp = P.ob_hole[(size_t)t * cap_out + k];
+        if (hp < n_new) {
+            s_low[atomicAdd(&s_nlow, 1)] = hp;
+        } else {
+            const int b = hp - n_new;
+            atomicOr(&s_bits[b >> 5], 1u << (b & 31));
+        }
+    }
+    __syncthreads();
+    const int h_low = s_nlow;
+    const size_t base = (size_t)t * P.cap;
+    for (int q = 0; q < s_nnb; ++q) {
+        const int nb = s_nb[q], no = P.ob_count[nb];
+        for (int k = threadIdx.x; k < no; k += NT) {
+            const size_t o = (size_t)nb * cap_out + k;
+            const int c = P.ob_cell[o];
+            if (c >= 0 && cell_x(c) / TX + (cell_y(c) / TY) * d.ntx == t) {
+                const int i = atomicAdd(&s_ctr, 1);
+                const int dl = i < h_low ? s_low[i] : n_old + (i - h_low);
+                if (i < I && dl < P.cap) {
+                    const size_t dst = base + dl;
+                    P.cell[dst] = c;
+                    P.x[dst] = P.ob_x[o];
+                    P.y[dst] = P.ob_y[o];
+                    P.ux[dst] = P.ob_ux[o];
+                    P.uy[dst] = P.ob_uy[o];
+                    P.uz[dst] = P.ob_uz[o];
+                }
+            }
+        }
+    }
+    // live particles of the tail [n_new, n_old) fill the remaining low holes
+    for (int pos = n_new + threadIdx.x; pos < n_old; pos += NT) {
+        const int b = pos - n_new;
+        if (!((s_bits[b >> 5] >> (b & 31)) & 1u)) {
+            const int i = I + atomicAdd(&s_ctr2, 1);
+            if (i >= h_low) {  // the hole bookkeeping is inconsistent: flag, never write
+                atomicOr(&d.st->err, ERR_CAPACITY);
+                continue;
+            }
+            const size_t src = base + pos, dst = base + s_low[i];
+            P.cell[dst] = P.cell[src];
+            P.x[dst] = P.x[src];
+            P.y[dst] = P.y[src];
+            P.ux[dst] = P.ux[src];
+            P.uy[dst] = P.uy[src];
+            P.uz[dst] = P.uz[src];
+        }
+    }
+    if (threadIdx.x == 0) P.count[t] = n_new;
+}
+
+// ---------------------------------------------------------------------------
+// row a5: fold the per-tile blocks into the global planes.  Each cell sums, in
+// a fixed order, the block entries of the (up to 9) tile images whose block
+// covers it; gap columns of the moving window are cleared (current deposited
+// beyond the window is dropped).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(NT) void k_fold(SimDev<R> d, int nplanes, R *o0, R *o1, R *o2)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    const int origin = d.st->origin;
+    for (int k = threadIdx.x; k < w * h; k += NT) {
+        const int lx = k % w, ly = k / w;
+        const int gx = x0 + lx, gy = y0 + ly;
+        R a0 = 0, a1 = 0, a2 = 0;
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int tyn = wrapi(ty + oy, d.nty);
+            const int hn = min(TY, d.ny - tyn * TY);
+            const int py = oy == 0 ? ly : (oy < 0 ? ly + hn : ly - h);
+            if (py < -1 || py >= hn + 2) continue;
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int txn = wrapi(tx + ox, d.ntx);
+                const int wn = min(TX, d.nxs - txn * TX);
+                const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
+                if (px < -1 || px >= wn + 2) continue;
+                const R *b = d.blk + (size_t)(txn + tyn * d.ntx) * 3 * BP + (px + 1) +
+                             (py + 1) * PX;
+                a0 += b[0];
+                if (nplanes > 1) {
+                    a1 += b[BP];
+                    a2 += b[2 * BP];
+                }
+            }
+        }
+        const bool gap = d.window && window_col(gx, origin, d.nxs) >= d.nx;
+        const size_t g = (size_t)gx + (size_t)gy * d.nxs;
+        o0[g] = gap ? R(0) : a0;
+        if (nplanes > 1) {
+            o1[g] = gap ? R(0) : a1;
+            o2[g] = gap ? R(0) : a2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row a6: binomial filter.  Per tile: load the planes with a halo of
+// npass + compensate cells, apply the x passes (binomial, then compensator),
+// then the y passes, keeping the gap at zero; write the interior.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(NT) void k_filter(SimDev<R> d, int nplanes, const R *i0,
+                                               const R *i1, const R *i2, R *o0, R *o1, R *o2)
+{
+    __shared__ R sa[QX * QY];
+    __shared__ R sb[QX * QY];
+    __shared__ unsigned char s_gap[QX];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    const int origin = d.st->origin;
+    const int rf = d.npass + (d.compensate ? 1 : 0);
+    const R N = (R)d.npass;
+    for (int k = threadIdx.x; k < QX; k += NT) {
+        int gx = (x0 + k - MAX_FR) % d.nxs;
+        gx += gx < 0 ? d.nxs : 0;
+        s_gap[k] = d.window && window_col(gx, origin, d.nxs) >= d.nx;
+    }
+    for (int pl = 0; pl < nplanes; ++pl) {
+        const R *in = pl == 0 ? i0 : (pl == 1 ? i1 : i2);
+        R *out = pl == 0 ? o0 : (pl == 1 ? o1 : o2);
+        __syncthreads();
+        for (int k = threadIdx.x; k < QX * QY; k += NT) {
+            const int lx = k % QX - MAX_FR, ly = k / QX - MAX_FR;
+            R v = R(0);
+            if (lx >= -rf && lx < w + rf && ly >= -rf && ly < h + rf) {
+                // the halo may reach beyond one period on tiny grids
+                int gx = (x0 + lx) % d.nxs;
+                gx += gx < 0 ? d.nxs : 0;
+                int gy = (y0 + ly) % d.ny;
+                gy += gy < 0 ? d.ny : 0;
+                v = in[(size_t)gx + (size_t)gy * d.nxs];
+            }
+            sa[k] = v;
+            sb[k] = R(0);
+        }
+        __syncthreads();
+        R *a = sa, *b = sb;
+        for (int pass = 0; pass < rf; ++pass) {
+            const bool comp = pass == d.npass;
+            const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+            for (int k = threadIdx.x; k < QX * QY; k += NT) {
+                const int i = k % QX;
+                R v = R(0);
+                if (i > 0 && i < QX - 1 && !s_gap[i]) v = w0 * a[k - 1] + w1 * a[k] + w0 * a[k + 1];
+                b[k] = v;
+            }
+            __syncthreads();
+            R *tmp = a;
+            a = b;
+            b = tmp;
+        }
+        for (int pass = 0; pass < rf; ++pass) {
+            const bool comp = pass == d.npass;
+            const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+            for (int k = threadIdx.x; k < QX * QY; k += NT) {
+                const int j = k / QX;
+                R v = R(0);
+                if (j > 0 && j < QY - 1) v = w0 * a[k - QX] + w1 * a[k] + w0 * a[k + QX];
+                b[k] = v;
+            }
+            __syncthreads();
+            R *tmp = a;
+            a = b;
+            b = tmp;
+        }
+        for (int k = threadIdx.x; k < w * h; k += NT) {
+            const int lx = k % w, ly = k / w;
+            out[(size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs] =
+                a[(lx + MAX_FR) + (ly + MAX_FR) * QX];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row a7: Yee step B half, E full, B half on a tile with its guard halo; reads
+// buffer `parity`, writes the other one.  Beyond the moving window every
+// component is held at zero after each sub-step, as zero guard cells would.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(NT) void k_yee(SimDev<R> d)
+{
+    __shared__ R e[3 * BP];
+    __shared__ R b[3 * BP];
+    __shared__ R jl[3 * BP];
+    __shared__ unsigned char s_gap[PX];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    const int par = d.st->parity, origin = d.st->origin;
+    for (int k = threadIdx.x; k < PX; k += NT)
+        s_gap[k] = d.window && window_col(wrapi(x0 + k - 1, d.nxs), origin, d.nxs) >= d.nx;
+    for (int k = threadIdx.x; k < BP; k += NT) {
+        const int lx = k % PX - 1, ly = k / PX - 1;
+        const bool in = lx < w + 2 && ly < h + 2;
+        const size_t g =
+            in ? (size_t)wrapi(x0 + lx, d.nxs) + (size_t)wrapi(y0 + ly, d.ny) * d.nxs : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R *Fe = par ? d.F[1][c] : d.F[0][c];
+            const R *Fb = par ? d.F[1][3 + c] : d.F[0][3 + c];
+            e[c * BP + k] = in ? Fe[g] : R(0);
+            b[c * BP + k] = in ? Fb[g] : R(0);
+            jl[c * BP + k] = in ? d.Jf[c][g] : R(0);
+        }
+    }
+    __syncthreads();
+    const R hdt = R(0.5) * d.dt;
+    // B half step on local [-1, w] x [-1, h]
+    for (int k = threadIdx.x; k < BP; k += NT) {
+        const int i = k % PX - 1, j = k / PX - 1;
+        if (i <= w && j <= h) {
+            const bool gp = s_gap[i + 1];
+            const R dEz_dy = (e[2 * BP + k + PX] - e[2 * BP + k]) * d.idy;
+            const R dEz_dx = (e[2 * BP + k + 1] - e[2 * BP + k]) * d.idx;
+            const R dEy_dx = (e[BP + k + 1] - e[BP + k]) * d.idx;
+            const R dEx_dy = (e[k + PX] - e[k]) * d.idy;
+            b[k] = gp ? R(0) : b[k] - hdt * dEz_dy;
+            b[BP + k] = gp ? R(0) : b[BP + k] + hdt * dEz_dx;
+            b[2 * BP + k] = gp ? R(0) : b[2 * BP + k] - hdt * (dEy_dx - dEx_dy);
+        }
+    }
+    __syncthreads();
+    // E full step on local [0, w] x [0, h]
+    for (int k = threadIdx.x; k < BP; k += NT) {
+        const int i = k % PX - 1, j = k / PX - 1;
+        if (i >= 0 && j >= 0 && i <= w && j <= h) {
+            const bool gp = s_gap[i + 1];
+            const R dBz_dy = (b[2 * BP + k] - b[2 * BP + k - PX]) * d.idy;
+            const R dBz_dx = (b[2 * BP + k] - b[2 * BP + k - 1]) * d.idx;
+            const R dBy_dx = (b[BP + k] - b[BP + k - 1]) * d.idx;
+            const R dBx_dy = (b[k] - b[k - PX]) * d.idy;
+            e[k] = gp ? R(0) : e[k] + d.dt * (dBz_dy - jl[k]);
+            e[BP + k] = gp ? R(0) : e[BP + k] + d.dt * (-dBz_dx - jl[BP + k]);
+            e[2 * BP + k] = gp ? R(0) : e[2 * BP + k] + d.dt * (dBy_dx - dBx_dy - jl[2 * BP + k]);
+        }
+    }
+    __syncthreads();
+    // B half step on the interior, and write out
+    const int npar = par ^ 1;
+    for (int k = threadIdx.x; k < BP; k += NT) {
+        const int i = k % PX - 1, j = k / PX - 1;
+        if (i >= 0 && j >= 0 && i < w && j < h) {
+            const bool gp = s_gap[i + 1];
+            const R dEz_dy = (e[2 * BP + k + PX] - e[2 * BP + k]) * d.idy;
+            const R dEz_dx = (e[2 * BP + k + 1] - e[2 * BP + k]) * d.idx;
+            const R dEy_dx = (e[BP + k + 1] - e[BP + k]) * d.idx;
+            const R dEx_dy = (e[k + PX] - e[k]) * d.idy;
+            const R nbx = gp ? R(0) : b[k] - hdt * dEz_dy;
+            const R nby = gp ? R(0) : b[BP + k] + hdt * dEz_dx;
+            const R nbz = gp ? R(0) : b[2 * BP + k] - hdt * (dEy_dx - dEx_dy);
+            const size_t g = (size_t)(x0 + i) + (size_t)(y0 + j) * d.nxs;
+            (npar ? d.F[1][0] : d.F[0][0])[g] = e[k];
+            (npar ? d.F[1][1] : d.F[0][1])[g] = e[BP + k];
+            (npar ? d.F[1][2] : d.F[0][2])[g] = e[2 * BP + k];
+            (npar ? d.F[1][3] : d.F[0][3])[g] = nbx;
+            (npar ? d.F[1][4] : d.F[0][4])[g] = nby;
+            (npar ? d.F[1][5] : d.F[0][5])[g] = nbz;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// end of step: flip the field buffers, count the step and decide the window
+// shift (the window advances one cell once iter*dt >= (nshift+1)*dx, in double)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_step_end(SimDev<R> d)
+{
+    if (threadIdx.x != 0) return;
+    DevState *st = d.st;
+    st->parity ^= 1;
+    st->iter += 1;
+    st->shift = 0;
+    if (d.window && (double)st->iter * d.dt_d >= (double)(st->nshift + 1) * d.dx_d) {
+        st->shift = 1;
+        st->nshift += 1;
+        st->origin = wrapi(st->origin + 1, d.nxs);
+    }
+}
+
+// Row a8, part 1 (blocks [0, nty*nsp)): particles of the column that left the
+// window are removed by a stable in-tile compaction; part 2 (block nty*nsp):
+// the six field planes of that column are cleared.  No-op unless shifted.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_window_clear(SimDev<R> d)
+{
+    __shared__ int s_w[NT / 64];
+    const DevState *st = d.st;
+    if (!st->shift) return;
+    const int col = wrapi(st->origin - 1, d.nxs);
+    const int par = st->parity;
+    if ((int)blockIdx.x == d.nty * d.nsp) {
+        for (int j = threadIdx.x; j < d.ny; j += NT) {
+            const size_t g = (size_t)col + (size_t)j * d.nxs;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) (par ? d.F[1][c] : d.F[0][c])[g] = R(0);
+        }
+        return;
+    }
+    const int ty = blockIdx.x % d.nty, s = blockIdx.x / d.nty;
+    const int t = col / TX + ty * d.ntx;
+    const SpDev<R> &P = d.sp[s];
+    const size_t base = (size_t)t * P.cap;
+    const int n = P.count[t];
+    int kept = 0;
+    for (int p0 = 0; p0 < n; p0 += NT) {
+        const int p = p0 + threadIdx.x;
+        int c = 0;
+        R x = 0, y = 0, ux = 0, uy = 0, uz = 0;
+        bool keep = false;
+        if (p < n) {
+            c = P.cell[base + p];
+            keep = cell_x(c) != col;
+            x = P.x[base + p];
+            y = P.y[base + p];
+            ux = P.ux[base + p];
+            uy = P.uy[base + p];
+            uz = P.uz[base + p];
+        }
+        int tot;
+        const int r = block_rank(keep, s_w, &tot);
+        if (keep) {
+            const size_t q = base + kept + r;
+            P.cell[q] = c;
+            P.x[q] = x;
+            P.y[q] = y;
+            P.ux[q] = ux;
+            P.uy[q] = uy;
+            P.uz[q] = uz;
+        }
+        kept += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) P.count[t] = kept;
+}
+
+// Row a8, part 3: load the column that entered at the right edge.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
+{
+    __shared__ int s_w[NT / 64];
+    const DevState *st = d.st;
+    if (!st->shift) return;
+    const int col = wrapi(st->origin + d.nx - 1, d.nxs);
+    const long long ilab = (long long)d.nx - 1 + st->nshift;
+    const int ty = blockIdx.x % d.nty, s = blockIdx.x / d.nty;
+    const int t = col / TX + ty * d.ntx;
+    const int y0 = ty * TY, h = min(TY, d.ny - y0);
+    const SpDev<R> &P = d.sp[s];
+    if (!(P.density > 0.0)) return;
+    const size_t base = (size_t)t * P.cap;
+    const int n0 = P.count[t];
+    const int ppc = P.ppc_x * P.ppc_y;
+    const int total = h * ppc;
+    int added = 0;
+    for (int q0 = 0; q0 < total; q0 += NT) {
+        const int q = q0 + threadIdx.x;
+        bool ok = false;
+        int j = 0, m = 0, l = 0;
+        if (q < total) {
+            const int sub = q / h;
+            j = y0 + q % h;
+            m = sub % P.ppc_x;
+            l = sub / P.ppc_x;
+            const double xo = ((double)m + 0.5) / (double)P.ppc_x;
+            const double xlab = ((double)ilab + xo) * d.dx_d;
+            ok = xlab >= P.x_lo && xlab < P.x_hi;
+        }
+        int tot;
+        const int r = block_rank(ok, s_w, &tot);
+        if (ok) {
+            const int pos = n0 + added + r;
+            if (pos < P.cap) {
+                R u[3];
+                maxwellian(P, d.key0, d.key1, (uint32_t)ilab, (uint32_t)j,
+                           (uint32_t)(l * P.ppc_x + m), (uint32_t)s, u);
+                const size_t o = base + pos;
+                P.cell[o] = pack_cell(col, j);
+                P.x[o] = (R)(((double)m + 0.5) / (double)P.ppc_x);
+                P.y[o] = (R)(((double)l + 0.5) / (double)P.ppc_y);
+                P.ux[o] = u[0];
+                P.uy[o] = u[1];
+                P.uz[o] = u[2];
+            } else {
+                atomicOr(&d.st->err, ERR_CAPACITY);
+            }
+        }
+        added += tot;
+    }
+    if (threadIdx.x == 0) P.count[t] = min(n0 + added, P.cap);
+}
+
+// Initial load of species s, one block per tile.  Particles are stored
+// sub-position major, cell minor, so that consecutive particles (one
+// wavefront) sit in different cells and their LDS atomics rarely collide.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
+{
+    __shared__ int s_w[NT / 64];
+    const int t = blockIdx.x;
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    const SpDev<R> &P = d.sp[s];
+    const int origin = d.st->origin, nshift = d.st->nshift;
+    const size_t base = (size_t)t * P.cap;
+    const int ncell = w * h, ppc = P.ppc_x * P.ppc_y;
+    const int total = ncell * ppc;
+    int added = 0;
+    for (int q0 = 0; q0 < total; q0 += NT) {
+        const int q = q0 + threadIdx.x;
+        bool ok = false;
+        int gx = 0, gy = 0, m = 0, l = 0;
+        long long ilab = 0;
+        if (q < total && P.density > 0.0) {
+            const int sub = q / ncell, c = q % ncell;
+            gx = x0 + c % w;
+            gy = y0 + c / w;
+            m = sub % P.ppc_x;
+            l = sub / P.ppc_x;
+            const int wc = d.window ? window_col(gx, origin, d.nxs) : gx;
+            ilab = (long long)wc + nshift;
+            const double xo = ((double)m + 0.5) / (double)P.ppc_x;
+            const double xlab = ((double)ilab + xo) * d.dx_d;
+            ok = wc < d.nx && xlab >= P.x_lo && xlab < P.x_hi;
+        }
+        int tot;
+        const int r = block_rank(ok, s_w, &tot);
+        if (ok) {
+            const int pos = added + r;
+            if (pos < P.cap) {
+                R u[3];
+                maxwellian(P, d.key0, d.key1, (uint32_t)ilab, (uint32_t)gy,
+                           (uint32_t)(l * P.ppc_x + m), (uint32_t)s, u);
+                const size_t o = base + pos;
+                P.cell[o] = pack_cell(gx, gy);
+                P.x[o] = (R)(((double)m + 0.5) / (double)P.ppc_x);
+                P.y[o] = (R)(((double)l + 0.5) / (double)P.ppc_y);
+                P.ux[o] = u[0];
+                P.uy[o] = u[1];
+                P.uz[o] = u[2];
+            } else {
+                atomicOr(&d.st->err, ERR_CAPACITY);
+            }
+        }
+        added += tot;
+    }
+    if (threadIdx.x == 0) P.count[t] = min(added, P.cap);
+}
+
+// ---------------------------------------------------------------------------
+// row a9: diagnostics (FP64 reductions)
+// ---------------------------------------------------------------------------
+// charge density on the nodes: per-tile LDS deposit of bilinear weights,
+// flushed to plane 0 of the tile blocks (folded afterwards)
+template <typename R>
+__global__ __launch_bounds__(NT) void k_rho(SimDev<R> d)
+{
+    __shared__ R sr[BP];
+    const int t = blockIdx.x;
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    for (int k = threadIdx.x; k < BP; k += NT) sr[k] = R(0);
+    __syncthreads();
+    for (int s = 0; s < d.nsp; ++s) {
+        const SpDev<R> &P = d.sp[s];
+        const int n = P.count[t];
+        const size_t base = (size_t)t * P.cap;
+        for (int p = threadIdx.x; p < n; p += NT) {
+            const int c = P.cell[base + p];
+            const R x = P.x[base + p], y = P.y[base + p];
+            const int k = (cell_x(c) - x0 + 1) + (cell_y(c) - y0 + 1) * PX;
+            lds_add(sr + k, P.qp * (R(1) - x) * (R(1) - y));
+            lds_add(sr + k + 1, P.qp * x * (R(1) - y));
+            lds_add(sr + k + PX, P.qp * (R(1) - x) * y);
+            lds_add(sr + k + PX + 1, P.qp * x * y);
+        }
+    }
+    __syncthreads();
+    R *out = d.blk + (size_t)t * 3 * BP;
+    for (int k = threadIdx.x; k < BP; k += NT) out[k] = sr[k];
+}
+
+template <typename R>
+__device__ __forceinline__ double div_at(const R *fx, const R *fy, const SimDev<R> &d, int gx,
+                                         int gy, int origin)
+{
+    // backward differences at node (gx, gy) of an (x-staggered, y-staggered)
+    // pair; values beyond the window are zero
+    const int xm = wrapi(gx - 1, d.nxs), ym = wrapi(gy - 1, d.ny);
+    const size_t g = (size_t)gx + (size_t)gy * d.nxs;
+    double vxm = (double)fx[(size_t)xm + (size_t)gy * d.nxs];
+    if (d.window && window_col(xm, origin, d.nxs) >= d.nx) vxm = 0.0;
+    return ((double)fx[g] - vxm) / d.dx_d +
+           ((double)fy[g] - (double)fy[(size_t)gx + (size_t)ym * d.nxs]) / d.dy_d;
+}
+
+// g0 = div E^0 - F rho^0 (rho_f must hold F rho^0)
+template <typename R>
+__global__ __launch_bounds__(NT) void k_g0(SimDev<R> d)
+{
+    const int par = d.st->parity, origin = d.st->origin;
+    const R *ex = par ? d.F[1][0] : d.F[0][0];
+    const R *ey = par ? d.F[1][1] : d.F[0][1];
+    const long long ncell = (long long)d.nxs * d.ny;
+    for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < ncell;
+         g += (long long)gridDim.x * NT) {
+        const int gx = (int)(g % d.nxs), gy = (int)(g / d.nxs);
+        const bool gap = d.window && window_col(gx, origin, d.nxs) >= d.nx;
+        d.g0[g] = gap ? 0.0 : div_at(ex, ey, d, gx, gy, origin) - (double)d.rho_f[g];
+    }
+}
+
+__device__ double block_sum(double v, double *s)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max(double v, double *s)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+// field energy and the Gauss / continuity residuals, per block partials:
+// red[b*5 + {0: E^2, 1: B^2, 2: gauss max, 3: continuity max, 4: |rho| max}]
+template <typename R>
+__global__ __launch_bounds__(NT) void k_diag_grid(SimDev<R> d, int has_prev)
+{
+    __shared__ double sred[NT];
+    const int par = d.st->parity, origin = d.st->origin;
+    const R *F[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) F[c] = par ? d.F[1][c] : d.F[0][c];
+    const long long ncell = (long long)d.nxs * d.ny;
+    double e2 = 0, b2 = 0, gm = 0, cm = 0, rm = 0;
+    const double idt = 1.0 / d.dt_d;
+    for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < ncell;
+         g += (long long)gridDim.x * NT) {
+        const int gx = (int)(g % d.nxs), gy = (int)(g / d.nxs);
+        if (d.window && window_col(gx, origin, d.nxs) >= d.nx) continue;
+        const double ex = F[0][g], ey = F[1][g], ez = F[2][g];
+        const double bx = F[3][g], by = F[4][g], bz = F[5][g];
+        e2 += ex * ex + ey * ey + ez * ez;
+        b2 += bx * bx + by * by + bz * bz;
+        const double gres = div_at(F[0], F[1], d, gx, gy, origin) - (double)d.rho_f[g] - d.g0[g];
+        gm = fmax(gm, fabs(gres));
+        rm = fmax(rm, fabs((double)d.rho[g]));
+        if (has_prev) {
+            const double cres = ((double)d.rho[g] - (double)d.rho_prev[g]) * idt +
+                                div_at(d.J[0], d.J[1], d, gx, gy, origin);
+            cm = fmax(cm, fabs(cres));
+        }
+    }
+    e2 = block_sum(e2, sred);
+    b2 = block_sum(b2, sred);
+    gm = block_max(gm, sred);
+    cm = block_max(cm, sred);
+    rm = block_max(rm, sred);
+    if (threadIdx.x == 0) {
+        double *r = d.red + (size_t)blockIdx.x * 5;
+        r[0] = e2;
+        r[1] = b2;
+        r[2] = gm;
+        r[3] = cm;
+        r[4] = rm;
+    }
+}
+
+// kinetic energy per tile and species with u- = u + (q/m)(dt/2) E^n(x^n):
+// red[NB_DIAG*5 + t*MAX_SP + s]
+template <typename R>
+__global__ __launch_bounds__(NT) void k_diag_ke(SimDev<R> d)
+{
+    __shared__ R sf[6 * BP];
+    __shared__ double sred[NT];
+    const int t = blockIdx.x;
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    load_tile_fields(d, d.st->parity, x0, y0, w, h, sf, (R *)nullptr);
+    __syncthreads();
+    for (int s = 0; s < d.nsp; ++s) {
+        const SpDev<R> &P = d.sp[s];
+        const int n = P.count[t];
+        const size_t base = (size_t)t * P.cap;
+        const double mp = (double)P.qp / (double)P.qm;
+        double ke = 0;
+        for (int p = threadIdx.x; p < n; p += NT) {
+            const int c = P.cell[base + p];
+            const R x = P.x[base + p], y = P.y[base + p];
+            const int lx = cell_x(c) - x0, ly = cell_y(c) - y0;
+            const bool lox = x < R(0.5), loy = y < R(0.5);
+            const int ixh = lx - (lox ? 1 : 0), iyh = ly - (loy ? 1 : 0);
+            const R wxh = x + (lox ? R(0.5) : R(-0.5)), wyh = y + (loy ? R(0.5) : R(-0.5));
+            const double ex = lerp2(sf, ixh, ly, wxh, y);
+            const double ey = lerp2(sf + BP, lx, iyh, x, wyh);
+            const double ez = lerp2(sf + 2 * BP, lx, ly, x, y);
+            const double tau = (double)P.tau;
+            const double a = (double)P.ux[base + p] + tau * ex;
+            const double b = (double)P.uy[base + p] + tau * ey;
+            const double cc = (double)P.uz[base + p] + tau * ez;
+            const double u2 = a * a + b * b + cc * cc;
+            ke += mp * u2 / (sqrt(1.0 + u2) + 1.0);
+        }
+        ke = block_sum(ke, sred);
+        if (threadIdx.x == 0) d.red[(size_t)NB_DIAG * 5 + (size_t)t * MAX_SP + s] = ke;
+    }
+}
+
+// final fixed-order reduction of the partials into d.res:
+// [0] E energy, [1] B energy, [2..5] KE per species, [6] gauss max,
+// [7] continuity max, [8] |rho| max
+template <typename R>
+__global__ __launch_bounds__(NT) void k_diag_final(SimDev<R> d)
+{
+    __shared__ double sred[NT];
+    const double area = d.dx_d * d.dy_d;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < NB_DIAG; b += NT) {
+        const double *r = d.red + (size_t)b * 5;
+        v[0] += r[0];
+        v[1] += r[1];
+        v[2] = fmax(v[2], r[2]);
+        v[3] = fmax(v[3], r[3]);
+        v[4] = fmax(v[4], r[4]);
+    }
+    const double e2 = block_sum(v[0], sred), b2 = block_sum(v[1], sred);
+    const double gm = block_max(v[2], sred), cm = block_max(v[3], sred);
+    const double rm = block_max(v[4], sred);
+    for (int s = 0; s < d.nsp; ++s) {
+        double k = 0;
+        for (int t = threadIdx.x; t < d.ntiles; t += NT)
+            k += d.red[(size_t)NB_DIAG * 5 + (size_t)t * MAX_SP + s];
+        k = block_sum(k, sred);
+        if (threadIdx.x == 0) d.res[2 + s] = k * area;
+    }
+    if (threadIdx.x == 0) {
+        d.res[0] = 0.5 * e2 * area;
+        d.res[1] = 0.5 * b2 * area;
+        d.res[6] = gm;
+        d.res[7] = cm;
+        d.res[8] = rm;
+    }
+}
+
+template <typename R>
+__global__ void k_copy(const R *src, R *dst, long long n)
+{
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n;
+         i += (long long)gridDim.x * NT)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename R>
+hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::migrate(const SimDev<R> &d, hipStream_t s)
+{
+    if (d.nsp == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_migrate<R>, dim3(d.ntiles, d.nsp), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold<R>, dim3(d.ntiles), dim3(NT), 0, s, d, nplanes, o0, o1, o2);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
+                             const R *i2, R *o0, R *o1, R *o2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_filter<R>, dim3(d.ntiles), dim3(NT), 0, s, d, nplanes, i0, i1, i2, o0,
+                       o1, o2);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_yee<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::step_end(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_end<R>, dim3(1), dim3(64), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::window(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_window_clear<R>, dim3(d.nty * d.nsp + 1), dim3(NT), 0, s, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || d.nsp == 0) return e;
+    hipLaunchKernelGGL(k_window_inject<R>, dim3(d.nty * d.nsp), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::load(const SimDev<R> &d, int sp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_load<R>, dim3(d.ntiles), dim3(NT), 0, s, d, sp);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::rho(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rho<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::g0(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_g0<R>, dim3(NB_DIAG), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::diag(const SimDev<R> &d, int has_prev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diag_grid<R>, dim3(NB_DIAG), dim3(NT), 0, s, d, has_prev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_ke<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final<R>, dim3(1), dim3(NT), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::copy_plane(const R *src, R *dst, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy<R>, dim3(NB_DIAG), dim3(NT), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace pic

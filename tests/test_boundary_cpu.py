@@ -1,0 +1,105 @@
+"""CPU checks of the C ABI boundary: the built library loads, exports every
+function include/pic.h declares, and its host-side validation (configuration,
+Courant limit, arena size) answers without touching a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from inputs import clouds1024, lwfa, lwfa8000, thermal64
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+LIB = os.path.join(ROOT, "paper_2106_12485_amd", "libpic.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(pic_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def libpic():
+    if not os.path.exists(LIB):
+        from paper_2106_12485_amd import build
+        build.build(force=False)
+    from paper_2106_12485_amd import pic
+    return pic.lib()
+
+
+def test_header_declares_the_hot_path_calls():
+    names = declared_functions()
+    for n in ("pic_init", "pic_step", "pic_deposit", "pic_field_advance", "pic_energy",
+              "pic_mem_bytes", "pic_free", "pic_set_particles", "pic_get_particles",
+              "pic_set_fields", "pic_get_fields", "pic_get_current", "pic_status"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(libpic):
+    for n in declared_functions():
+        assert hasattr(libpic, n), n
+
+
+def test_mem_bytes_of_the_workloads(libpic):
+    from paper_2106_12485_amd import mem_bytes
+    for w in (thermal64(), lwfa(), clouds1024(), lwfa8000()):
+        n = mem_bytes(w)
+        # at least the particle state of the initial load
+        assert n > w.n_particles_initial() * 24
+        assert mem_bytes(w, fp64=True) > n
+    # clouds: 2 species x 4096 tiles x (3 x 16 ppc x 256) slots x 24 B dominate
+    assert mem_bytes(clouds1024()) < 4 * 2 ** 30
+
+
+def test_validation_rejects_bad_configurations(libpic):
+    from paper_2106_12485_amd import pic
+    w = thermal64()
+    good = pic.make_cfg(w)
+    assert libpic.pic_mem_bytes(C.byref(good)) > 0
+
+    def bad(**kw):
+        c = pic.make_cfg(w)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        assert libpic.pic_mem_bytes(C.byref(c)) == 0
+        return libpic.pic_last_error().decode()
+
+    assert "Courant" in bad(dt=0.1 / math.sqrt(2) * 1.0001)
+    assert "nx" in bad(nx=1)
+    assert "16" in bad(nx=33)
+    assert "n_species" in bad(n_species=5)
+    assert "filter" in bad(filter_passes=0, filter_compensate=1)
+    assert "filter" in bad(filter_passes=4, filter_compensate=1)
+    c = pic.make_cfg(w)
+    c.sp[0].ppc_x = 0
+    assert libpic.pic_mem_bytes(C.byref(c)) == 0
+
+
+def test_init_error_codes_before_any_device_work(libpic):
+    from paper_2106_12485_amd import pic
+    w = thermal64()
+    h = C.c_void_p()
+    c = pic.make_cfg(w)
+    c.dt = 0.2
+    assert libpic.pic_init(C.byref(c), C.c_void_p(256), 1 << 40, None, C.byref(h)) == pic.PIC_E_CFL
+    c = pic.make_cfg(w)
+    need = libpic.pic_mem_bytes(C.byref(c))
+    assert libpic.pic_init(C.byref(c), C.c_void_p(256), need - 1, None,
+                           C.byref(h)) == pic.PIC_E_NOMEM
+    assert libpic.pic_init(C.byref(c), C.c_void_p(260), need, None,
+                           C.byref(h)) == pic.PIC_E_ARG
+    assert not h.value
+    assert libpic.pic_strerror(pic.PIC_E_CAPACITY) == b"particle capacity exceeded"
+
+
+def test_binding_fails_loudly_without_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2106_12485_amd import Simulation
+    with pytest.raises(RuntimeError):
+        Simulation(thermal64())

@@ -1,0 +1,297 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Each one-step test drives both sides from the same state (FP32-representable
+particles and fields) and compares the current before and after the filter,
+the six field planes and the particle set after one step.  Tolerance: relative
+L2 <= 1e-5 per quantity for the FP32 path, 1e-11 for the FP64 path.
+"""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+from inputs import LaserSpec, SpeciesSpec, Workload, clouds1024, lwfa, random_particles, thermal64
+from parity_util import (TOL_STEP_FP32, TOL_STEP_FP64, add_species, compare_particles,
+                         oracle_from_workload, oracle_mirror, rel_l2, round_to_f32)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - the GPU suite runs on a GPU machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2106_12485_amd import PIC_E_CAPACITY, PicError, Simulation  # noqa: E402
+
+
+def tol(fp64):
+    return TOL_STEP_FP64 if fp64 else TOL_STEP_FP32
+
+
+def step_both(sim, o, direct=False):
+    if direct:
+        sim.deposit()
+        sim.field_advance()
+    else:
+        sim.step(1)
+    o.step(1)
+
+
+def compare_state(sim, o, w, fp64=False, what=""):
+    t = tol(fp64)
+    errs = dict(J=rel_l2(sim.get_current(False), o.get_current(False)),
+                Jf=rel_l2(sim.get_current(True), o.get_current(True)),
+                F=rel_l2(sim.get_fields(), o.get_fields()))
+    for k in range(len(w.species)):
+        errs["p%d" % k] = compare_particles(sim.get_particles(k), o.get_particles(k), w.nx, w.ny,
+                                            window=w.moving_window, tol=t)
+    bad = {k: v for k, v in errs.items() if not v <= t}
+    assert not bad, (what, errs)
+    return errs
+
+
+def random_state(w, rng, uth=0.4, famp=0.2, n_per_species=None):
+    parts = []
+    for k, s in enumerate(w.species):
+        n = n_per_species or w.nx * w.ny * s.ppc[0] * s.ppc[1]
+        xr = (1, w.nx - 1) if w.moving_window else None
+        parts.append(round_to_f32(random_particles(rng, w.nx, w.ny, n, uth=uth, ufl=s.ufl,
+                                                   x_range=xr)))
+    f = (famp * rng.standard_normal((6, w.ny, w.nx))).astype(np.float32).astype(np.float64)
+    return parts, f
+
+
+def setup_pair(w, parts, f, fp64=False, it=0, nshift=0, capacity_factor=0.0):
+    sim = Simulation(w, fp64=fp64, load=False, capacity_factor=capacity_factor)
+    o = oracle_from_workload(w)
+    add_species(o, w, load=False)
+    for k, p in enumerate(parts):
+        sim.set_particles(k, p)
+        o.set_particles(k, p)
+    sim.set_fields(f)
+    o.set_fields(f)
+    if it or nshift:
+        sim.set_time(it, nshift)
+        o.set_iter(it, nshift)
+    return sim, o
+
+
+def two_species(nx, ny, lx, ly, dt=0.07, **kw):
+    sp = [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.3,) * 3),
+          SpeciesSpec(0.5, 0.5, ppc=(2, 1), uth=(0.2,) * 3, ufl=(0.3, -0.2, 0.1))]
+    return Workload("t", nx, ny, lx, ly, dt, 1, sp, **kw)
+
+
+CASES = {
+    # name: (workload, fp64, direct launches)
+    "ragged_40x36_comp": (two_species(40, 36, 4.0, 3.6, filter_passes=1, filter_compensate=True),
+                          False, False),
+    "ragged_40x36_fp64": (two_species(40, 36, 4.0, 3.6, filter_passes=1, filter_compensate=True),
+                          True, False),
+    "no_filter_direct": (two_species(34, 18, 3.4, 1.8, filter_passes=0), False, True),
+    "three_passes": (two_species(48, 32, 4.8, 3.2, filter_passes=3, filter_compensate=True),
+                     False, False),
+    "single_tile_4x4": (two_species(4, 4, 0.4, 0.4, filter_passes=1), False, False),
+    "single_tile_2x2": (two_species(2, 2, 0.2, 0.2, filter_passes=2), False, True),
+    "two_tiles_wrap_18x20": (two_species(18, 20, 1.8, 2.0, filter_passes=1), False, False),
+    "anisotropic_cells": (two_species(64, 20, 1.28, 4.0, dt=0.0185, filter_passes=1), False, False),
+    "window_60x20": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
+                                 filter_passes=1, filter_compensate=True), False, False),
+    "window_60x20_fp64": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
+                                      filter_passes=1, filter_compensate=True), True, True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_one_step_matches_oracle(name):
+    w, fp64, direct = CASES[name]
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    parts, f = random_state(w, rng)
+    # with the window, start one step before a shift so that it is exercised
+    it = 0
+    if w.moving_window:
+        it = int(math.ceil(3 * w.dx / w.dt)) - 1
+    nsh = int(it * w.dt / w.dx + 1e-12) if w.moving_window else 0
+    sim, o = setup_pair(w, parts, f, fp64=fp64, it=it, nshift=nsh)
+    step_both(sim, o, direct)
+    if w.moving_window:
+        assert o.nshift == nsh + 1
+    compare_state(sim, o, w, fp64, name)
+    assert sim.status() == 0
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_loader_matches_oracle(fp64):
+    w = Workload("load", 40, 34, 4.0, 3.4, 0.07, 1,
+                 [SpeciesSpec(-1.0, 1.0, 0.0, 2.0, (4, 2), (0.05, 0.1, 0.2), (0.6, 0.0, -0.1)),
+                  SpeciesSpec(-0.5, 0.7, 2.05, 4.0, (3, 3), (0.02,) * 3, (-0.6, 0.1, 0.0))],
+                 seed=0x5EED1234ABCD)
+    sim = Simulation(w, fp64=fp64)
+    o = oracle_from_workload(w)
+    add_species(o, w, load=True)
+    for k, s in enumerate(w.species):
+        pg, po = sim.get_particles(k), o.get_particles(k)
+        assert len(pg["ix"]) == len(po["ix"]) > 0
+
+        def order(p):
+            return np.lexsort((np.round(p["x"] * s.ppc[0] * 2), np.round(p["y"] * s.ppc[1] * 2),
+                               p["ix"], p["iy"]))
+        a, b = order(pg), order(po)
+        assert np.array_equal(pg["ix"][a], po["ix"][b])
+        assert np.array_equal(pg["iy"][a], po["iy"][b])
+        t = 1e-15 if fp64 else 1e-7
+        for c in ("x", "y"):
+            assert np.abs(pg[c][a] - po[c][b]).max() <= t
+        for c in ("ux", "uy", "uz"):
+            assert np.abs(pg[c][a] - po[c][b]).max() <= (1e-14 if fp64 else 1e-6) * (
+                1 + np.abs(po[c]).max())
+
+
+def test_laser_initial_fields_match_oracle():
+    w = lwfa(nx=400, ny=64, lx=8.0, ly=12.8, steps=1, x_plasma=6.0)
+    w.laser = LaserSpec(2.0, 10.0, 4.0, 2.0, 3.0, 5.0, 6.4, math.pi / 3)
+    sim = Simulation(w)
+    o = oracle_from_workload(w)
+    add_species(o, w, load=True)
+    fg, fo = sim.get_fields(), o.get_fields()
+    assert np.abs(fo).max() > 10
+    assert np.abs(fg - fo).max() <= 2e-6 * np.abs(fo).max()
+
+
+def test_multi_step_migration_then_teacher_forced_step():
+    # fast particles in a small box: many tile crossings per step
+    w = two_species(40, 36, 4.0, 3.6, filter_passes=1, filter_compensate=True)
+    rng = np.random.default_rng(11)
+    parts, f = random_state(w, rng, uth=0.8, famp=0.1)
+    sim, o = setup_pair(w, parts, f)
+    n0 = [sim.count(k) for k in range(2)]
+    sim.step(25)
+    assert [sim.count(k) for k in range(2)] == n0
+    assert sim.status() == 0
+    om = oracle_mirror(sim, w)
+    step_both(sim, om)
+    compare_state(sim, om, w, False, "after 25 steps")
+
+
+def test_graph_replay_equals_direct_launches():
+    w = two_species(40, 36, 4.0, 3.6, filter_passes=1, filter_compensate=True)
+    rng = np.random.default_rng(12)
+    parts, f = random_state(w, rng)
+    a, _ = setup_pair(w, parts, f)
+    b, _ = setup_pair(w, parts, f)
+    a.step(10)
+    for _ in range(10):
+        b.deposit()
+        b.field_advance()
+    assert rel_l2(a.get_fields(), b.get_fields()) < 1e-5
+    for k in range(2):
+        assert compare_particles(a.get_particles(k), b.get_particles(k), w.nx, w.ny) < 1e-5
+
+
+def test_set_get_roundtrip_is_exact():
+    w = two_species(40, 36, 4.0, 3.6)
+    rng = np.random.default_rng(13)
+    parts, f = random_state(w, rng)
+    sim, _ = setup_pair(w, parts, f)
+    assert np.array_equal(sim.get_fields(), f)
+    for k, p in enumerate(parts):
+        q = sim.get_particles(k)
+        a = np.lexsort((p["x"], p["y"], p["ix"], p["iy"]))
+        b = np.lexsort((q["x"], q["y"], q["ix"], q["iy"]))
+        for c in ("ix", "iy", "x", "y", "ux", "uy", "uz"):
+            assert np.array_equal(np.asarray(p[c])[a], q[c][b]), c
+
+
+def test_thermal_64x64_invariants_and_oracle_parity():
+    """The 64x64 thermal plasma (16 ppc, uth 0.1, 100 steps): teacher-forced
+    one-step parity at steps 0, 50 and 99; Gauss and continuity residuals at
+    FP32 round-off every 10 steps; energy within the oracle's own
+    particle-order spread."""
+    w = thermal64()
+    sim = Simulation(w)
+    o = oracle_from_workload(w)
+    add_species(o, w, load=True)
+    assert sim.count(0) == o.count(0) == 65536
+    e0g, e0o = sim.energy(), o.energy()
+    assert abs(e0g["total"] - e0o["total"]) / e0o["total"] < 1e-6
+    for n in range(100):
+        if n in (0, 50, 99):
+            om = oracle_mirror(sim, w)
+            step_both(sim, om)
+            compare_state(sim, om, w, False, "step %d" % n)
+        else:
+            sim.step(1)
+        if n % 10 == 9:
+            e = sim.energy()
+            scale = e["rho_max"]
+            # FP32 round-off of rho (~64 terms per node) and of the E updates
+            assert e["gauss_res_max"] < 1e-4 * max(scale, 1.0), e
+    # continuity residual needs two diagnostics one step apart
+    sim.energy()
+    sim.step(1)
+    e = sim.energy()
+    assert 0 <= e["cont_res_max"] < 2e-4 * e["rho_max"] / w.dt, e
+    o.step(101)
+    eg, eo = e["total"], o.energy()["total"]
+    # free-running FP32 vs FP64: the paper's yardstick (Sec. 4.2) is the
+    # round-off of the deposit order; bound it by 1e-3 of the total
+    assert abs(eg - eo) / e0o["total"] < 1e-3, (eg, eo)
+
+
+def test_capacity_overflow_is_reported():
+    w = thermal64()
+    with pytest.raises(PicError) as ei:
+        Simulation(w, capacity_factor=0.5)
+    assert ei.value.code == PIC_E_CAPACITY
+    # slots exactly equal to the initial load of a full tile: net inflow into
+    # any tile overflows and the device flag is raised
+    sim = Simulation(w, capacity_factor=1.0)
+    sim.step(20)
+    assert sim.status() == PIC_E_CAPACITY
+    assert sim.energy()["status"] == PIC_E_CAPACITY
+
+
+def test_lwfa_window_run_counts_and_teacher_forced_shift():
+    # reduced laser-wakefield geometry with the moving window
+    w = lwfa(nx=300, ny=32, lx=6.0, ly=6.4, steps=40, x_plasma=4.0, ppc=(2, 2))
+    w.laser = LaserSpec(2.0, 10.0, 1.5, 1.0, 2.0, 3.0, 3.2, math.pi / 2)
+    sim = Simulation(w)
+    o = oracle_from_workload(w)
+    add_species(o, w, load=True)
+    assert sim.count(0) == o.count(0)
+    for n in range(30):
+        if n in (0, 13, 27):
+            om = oracle_mirror(sim, w)
+            step_both(sim, om)
+            compare_state(sim, om, w, False, "window step %d" % n)
+        else:
+            sim.step(1)
+    e = sim.energy()
+    assert e["nshift"] == int(30 * w.dt / w.dx + 1e-9)
+    o.step(30)
+    assert o.nshift == e["nshift"]
+    # cold plasma: the count changes only through the columns that leave and enter
+    assert abs(sim.count(0) - o.count(0)) <= 8
+
+
+def _full_size_parity(w, nsteps):
+    sim = Simulation(w)
+    n0 = sim.count(0)
+    assert n0 > 0
+    sim.step(nsteps)
+    assert sim.status() == 0
+    om = oracle_mirror(sim, w)
+    step_both(sim, om)
+    return compare_state(sim, om, w, False, w.name)
+
+
+def test_clouds_1024_full_size_teacher_forced():
+    w = clouds1024()
+    errs = _full_size_parity(w, 5)
+    assert errs["J"] < TOL_STEP_FP32
+
+
+def test_lwfa_2000x256_full_size_teacher_forced():
+    w = lwfa()
+    errs = _full_size_parity(w, 12)
+    assert errs["F"] < TOL_STEP_FP32
