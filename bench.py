@@ -49,7 +49,23 @@ def parse():
                     help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up and timed steps only (for rocprofv3)")
+    ap.add_argument("--direct", action="store_true",
+                    help="with --profile-only: launch kernels directly, not from the graph")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=n * 4, launches=5)))
 
 
 def cpu_baseline(w, nsteps):
@@ -86,11 +102,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     w = WORKLOADS[args.workload]()
     sim = Simulation(w, fp64=args.fp64)
     nparts = sum(sim.count(k) for k in range(len(w.species)))
     stream = sim.stream
 
+    if args.profile_only and args.direct:
+        sim.timing(True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     # timed region: K steps replayed from the captured step graph

@@ -153,6 +153,18 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->dt_dy = (R)(d->dt_d / d->dy_d);
     d->jxs = (R)(d->dx_d / d->dt_d);
     d->jys = (R)(d->dy_d / d->dt_d);
+    // Fixed-point scale 2^-e of the LDS sums.  One current or charge term of a
+    // particle is at most |q_p| (|v| < 1; weights and path fractions <= 1), so
+    // one LDS entry never exceeds the sum of |q_p| over the slots of the tile.
+    // Take the largest e that keeps that bound below 2^62.
+    double bound = 0.0;
+    for (int s = 0; s < c->n_species; ++s) {
+        const pic_species_cfg &p = c->sp[s];
+        bound += (double)L.cap[s] * p.density / (p.ppc_x * p.ppc_y);
+    }
+    const int e = bound > 0 ? std::min(120, 62 - (int)std::ceil(std::log2(bound))) : 60;
+    d->jq = (R)std::ldexp(1.0, sizeof(R) == 4 ? e - 32 : e);
+    d->jq_inv = std::ldexp(1.0, -e);
     d->key0 = (unsigned)(c->seed & 0xffffffffull);
     d->key1 = (unsigned)(c->seed >> 32);
     R *F = (R *)(a + L.off_F);

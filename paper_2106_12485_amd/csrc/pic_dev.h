@@ -74,6 +74,8 @@ struct SimDev {
     R dt_dx, dt_dy;   // dt/dx, dt/dy
     R jxs, jys;       // dx/dt, dy/dt
     double dx_d, dy_d, dt_d;
+    R jq;             // fixed-point scale: 2^(e-32) in FP32, 2^e in FP64
+    double jq_inv;    // 2^-e, value of one unit of an LDS sum
     unsigned key0, key1;
     R *F[2][6];       // ping-pong Ex Ey Ez Bx By Bz
     R *J[3];          // folded current of the last step
@@ -103,11 +105,48 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return x * q + (x < r ? x : r) + k;
 }
 
-template <typename R>
-__device__ __forceinline__ void lds_add(R *p, R v)
+// Current and charge are summed in LDS as 64-bit fixed point: integer LDS
+// atomics run at the rate of plain LDS traffic on CDNA, floating-point ones
+// do not, and integer sums do not depend on the order of the additions, so
+// the result is bitwise reproducible.  A term v becomes trunc-toward-minus-
+// infinity of v * 2^e.  FP32 builds the two words from the float directly:
+// with y = v * 2^(e-32) (jq = 2^(e-32)), the high word is floor(y) and the low
+// word (y - floor(y)) * 2^32, both exact; FP64 converts v * 2^e (jq = 2^e).
+__device__ __forceinline__ void lds_acc(unsigned long long *p, float v, float jq)
 {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const float y = v * jq;
+    const float hi = floorf(y);
+    const unsigned lo = (unsigned)((y - hi) * 4294967296.0f);
+    const unsigned long long q = ((unsigned long long)(unsigned)(int)hi << 32) | lo;
+    __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+__device__ __forceinline__ void lds_acc(unsigned long long *p, double v, double jq)
+{
+    const long long q = (long long)floor(v * jq);
+    __hip_atomic_fetch_add(p, (unsigned long long)q, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// element at a 32-bit byte offset from a wave-uniform base pointer (keeps the
+// address computation in 32 bits: base in SGPRs, offset in one VGPR)
+template <typename T>
+__device__ __forceinline__ T &at(T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+
+__device__ __forceinline__ double fx_value(unsigned long long q, double jq_inv)
+{
+    return (double)(long long)q * jq_inv;
+}
+
+// 1/x and 1/sqrt(x): the hardware approximations (about 1 ulp) in FP32, exact
+// division and square root in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt1(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt1(double x) { return 1.0 / sqrt(x); }
 
 __device__ __forceinline__ int pack_cell(int ix, int iy) { return ix | (iy << 16); }
 __device__ __forceinline__ int cell_x(int c) { return c & 0xffff; }

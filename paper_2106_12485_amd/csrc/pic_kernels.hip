@@ -92,9 +92,9 @@ __device__ void maxwellian(const SpDev<R> &P, uint32_t key0, uint32_t key1, uint
 // segment: weight at the midpoint +- (extent_x * extent_y)/12.
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ void deposit_segment(R *sj, int lx, int ly, R x, R y, R ddx, R ddy,
-                                                R vz, R qjx, R qjy, R qp, R ta, R tb, int cx,
-                                                int cy)
+__device__ __forceinline__ void deposit_segment(unsigned long long *sj, int lx, int ly, R x, R y,
+                                                R ddx, R ddy, R vz, R qjx, R qjy, R qp, R ta,
+                                                R tb, int cx, int cy, R jq)
 {
     const R f = tb - ta;
     const R tm = R(0.5) * (ta + tb);
@@ -104,45 +104,45 @@ __device__ __forceinline__ void deposit_segment(R *sj, int lx, int ly, R x, R y,
     const R ax = qjx * sx, ay = qjy * sy;
     const R az = qp * vz * f, corr = sx * sy * R(1.0 / 12.0);
     const int k = (lx + cx + 1) + (ly + cy + 1) * PX;
-    R *jx = sj, *jy = sj + BP, *jz = sj + 2 * BP;
-    lds_add(jx + k, ax * (R(1) - ym));
-    lds_add(jx + k + PX, ax * ym);
-    lds_add(jy + k, ay * (R(1) - xm));
-    lds_add(jy + k + 1, ay * xm);
-    lds_add(jz + k, az * ((R(1) - xm) * (R(1) - ym) + corr));
-    lds_add(jz + k + 1, az * (xm * (R(1) - ym) - corr));
-    lds_add(jz + k + PX, az * ((R(1) - xm) * ym - corr));
-    lds_add(jz + k + PX + 1, az * (xm * ym + corr));
+    unsigned long long *jx = sj, *jy = sj + BP, *jz = sj + 2 * BP;
+    lds_acc(jx + k, ax * (R(1) - ym), jq);
+    lds_acc(jx + k + PX, ax * ym, jq);
+    lds_acc(jy + k, ay * (R(1) - xm), jq);
+    lds_acc(jy + k + 1, ay * xm, jq);
+    lds_acc(jz + k, az * ((R(1) - xm) * (R(1) - ym) + corr), jq);
+    lds_acc(jz + k + 1, az * (xm * (R(1) - ym) - corr), jq);
+    lds_acc(jz + k + PX, az * ((R(1) - xm) * ym - corr), jq);
+    lds_acc(jz + k + PX + 1, az * (xm * ym + corr), jq);
 }
 
 // Split the straight move at the cell boundaries it crosses (at most one per
 // axis since |ddx|, |ddy| < 1), in the order the path crosses them.
 template <typename R>
-__device__ __forceinline__ void deposit_move(R *sj, int lx, int ly, R x, R y, R ddx, R ddy,
-                                             R vz, R qjx, R qjy, R qp)
+__device__ __forceinline__ void deposit_move(unsigned long long *sj, int lx, int ly, R x, R y,
+                                             R ddx, R ddy, R vz, R qjx, R qjy, R qp, R jq)
 {
     const R x1 = x + ddx, y1 = y + ddy;
     const int di = (x1 >= R(1)) - (x1 < R(0));
     const int dj = (y1 >= R(1)) - (y1 < R(0));
     R tx = R(1), ty = R(1);
-    if (di) tx = fmin(((di > 0 ? R(1) : R(0)) - x) / ddx, R(1));
-    if (dj) ty = fmin(((dj > 0 ? R(1) : R(0)) - y) / ddy, R(1));
+    if (di) tx = fmin(((di > 0 ? R(1) : R(0)) - x) * rcp(ddx), R(1));
+    if (dj) ty = fmin(((dj > 0 ? R(1) : R(0)) - y) * rcp(ddy), R(1));
     const bool xfirst = tx <= ty;
     const R t1 = xfirst ? tx : ty, t2 = xfirst ? ty : tx;
     if (t1 > R(0))
-        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, R(0), t1, 0, 0);
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, R(0), t1, 0, 0, jq);
     if (t2 > t1)
         deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t1, t2, xfirst ? di : 0,
-                        xfirst ? 0 : dj);
+                        xfirst ? 0 : dj, jq);
     if (R(1) > t2)
-        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t2, R(1), di, dj);
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t2, R(1), di, dj, jq);
 }
 
 // Load the six field planes of buffer `par` on the tile block (periodic wrap
 // in storage; gap columns hold zeros) and clear the current block.
 template <typename R>
 __device__ __forceinline__ void load_tile_fields(const SimDev<R> &d, int par, int x0, int y0,
-                                                 int w, int h, R *sf, R *sj)
+                                                 int w, int h, R *sf, unsigned long long *sj)
 {
     for (int k = threadIdx.x; k < BP; k += NT) {
         const int lx = k % PX - 1, ly = k / PX - 1;
@@ -155,9 +155,9 @@ __device__ __forceinline__ void load_tile_fields(const SimDev<R> &d, int par, in
             sf[c * BP + k] = in ? Fc[g] : R(0);
         }
         if (sj) {
-            sj[k] = R(0);
-            sj[BP + k] = R(0);
-            sj[2 * BP + k] = R(0);
+            sj[k] = 0ull;
+            sj[BP + k] = 0ull;
+            sj[2 * BP + k] = 0ull;
         }
     }
 }
@@ -169,7 +169,7 @@ template <typename R>
 __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
 {
     __shared__ R sf[6 * BP];
-    __shared__ R sj[3 * BP];
+    __shared__ unsigned long long sj[3 * BP];
     __shared__ int s_nout;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % d.ntx, ty = t / d.ntx;
@@ -182,23 +182,33 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
+    const R jq = d.jq;
     for (int s = 0; s < d.nsp; ++s) {
         const SpDev<R> &P = d.sp[s];
-        const int n = P.count[t];
+        const unsigned n = (unsigned)P.count[t];
         const size_t base = (size_t)t * P.cap;
+        // tile-uniform base pointers, indexed with 32-bit offsets
+        int *const pc = P.cell + base;
+        R *const px = P.x + base;
+        R *const py = P.y + base;
+        R *const pux = P.ux + base;
+        R *const puy = P.uy + base;
+        R *const puz = P.uz + base;
+        const size_t obase = (size_t)t * d.cap_out;
         const R qjx = P.qp * d.jxs, qjy = P.qp * d.jys;
-        for (int p0 = 0; p0 < n; p0 += NT) {
-            const int p = p0 + threadIdx.x;
+        const R tau = P.tau;
+        for (unsigned p0 = 0; p0 < n; p0 += NT) {
+            const unsigned p = p0 + threadIdx.x;
             bool leave = false, dead = false;
             int ncell = 0;
             R xn = 0, yn = 0, ux = 0, uy = 0, uz = 0;
+            const unsigned o4 = p * 4u, oR = p * (unsigned)sizeof(R);
             if (p < n) {
-                const size_t q = base + p;
-                const int cell = P.cell[q];
-                const R x = P.x[q], y = P.y[q];
-                ux = P.ux[q];
-                uy = P.uy[q];
-                uz = P.uz[q];
+                const int cell = at(pc, o4);
+                const R x = at(px, oR), y = at(py, oR);
+                ux = at(pux, oR);
+                uy = at(puy, oR);
+                uz = at(puz, oR);
                 const int ix = cell_x(cell), iy = cell_y(cell);
                 const int lx = ix - x0, ly = iy - y0;
                 // stage 1: each component from its own staggered grid
@@ -213,22 +223,21 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
                 const R by = lerp2(sf + 4 * BP, ixh, ly, wxh, y);
                 const R bz = lerp2(sf + 5 * BP, ixh, iyh, wxh, wyh);
                 // stage 2: relativistic Boris
-                const R tau = P.tau;
                 const R umx = ux + tau * ex, umy = uy + tau * ey, umz = uz + tau * ez;
-                const R ig = R(1) / sqrt(R(1) + umx * umx + umy * umy + umz * umz);
+                const R ig = rsqrt1(R(1) + umx * umx + umy * umy + umz * umz);
                 const R tvx = tau * bx * ig, tvy = tau * by * ig, tvz = tau * bz * ig;
                 const R upx = umx + (umy * tvz - umz * tvy);
                 const R upy = umy + (umz * tvx - umx * tvz);
                 const R upz = umz + (umx * tvy - umy * tvx);
-                const R fs = R(2) / (R(1) + tvx * tvx + tvy * tvy + tvz * tvz);
+                const R fs = R(2) * rcp(R(1) + tvx * tvx + tvy * tvy + tvz * tvz);
                 const R svx = fs * tvx, svy = fs * tvy, svz = fs * tvz;
                 ux = umx + (upy * svz - upz * svy) + tau * ex;
                 uy = umy + (upz * svx - upx * svz) + tau * ey;
                 uz = umz + (upx * svy - upy * svx) + tau * ez;
                 // move and stage 3
-                const R ig2 = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+                const R ig2 = rsqrt1(R(1) + ux * ux + uy * uy + uz * uz);
                 const R ddx = d.dt_dx * ux * ig2, ddy = d.dt_dy * uy * ig2;
-                deposit_move(sj, lx, ly, x, y, ddx, ddy, uz * ig2, qjx, qjy, P.qp);
+                deposit_move(sj, lx, ly, x, y, ddx, ddy, uz * ig2, qjx, qjy, P.qp, jq);
                 xn = x + ddx;
                 yn = y + ddy;
                 int di = (xn >= R(1)) - (xn < R(0));
@@ -243,12 +252,12 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
                 ncell = pack_cell(nix, niy);
                 leave = dead || (nix / TX + (niy / TY) * d.ntx) != t;
                 if (!leave) {
-                    P.cell[q] = ncell;
-                    P.x[q] = xn;
-                    P.y[q] = yn;
-                    P.ux[q] = ux;
-                    P.uy[q] = uy;
-                    P.uz[q] = uz;
+                    at(pc, o4) = ncell;
+                    at(px, oR) = xn;
+                    at(py, oR) = yn;
+                    at(pux, oR) = ux;
+                    at(puy, oR) = uy;
+                    at(puz, oR) = uz;
                 }
             }
             // row a4: wavefront ballot + prefix count gives each leaver its
@@ -261,8 +270,8 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
                 if (leave) {
                     const int slot = off + (int)__popcll(m & ((1ull << lane) - 1ull));
                     if (slot < d.cap_out) {
-                        const size_t o = (size_t)t * d.cap_out + slot;
-                        P.ob_hole[o] = p;
+                        const size_t o = obase + slot;
+                        P.ob_hole[o] = (int)p;
                         P.ob_cell[o] = dead ? -1 : ncell;
                         P.ob_x[o] = xn;
                         P.ob_y[o] = yn;
@@ -284,7 +293,8 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
     }
     // one flush of the tile's current block per step
     R *out = d.blk + (size_t)t * 3 * BP;
-    for (int k = threadIdx.x; k < 3 * BP; k += NT) out[k] = sj[k];
+    const double jqi = d.jq_inv;
+    for (int k = threadIdx.x; k < 3 * BP; k += NT) out[k] = (R)fx_value(sj[k], jqi);
 }
 
 // ---------------------------------------------------------------------------
@@ -808,11 +818,11 @@ __global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
 template <typename R>
 __global__ __launch_bounds__(NT) void k_rho(SimDev<R> d)
 {
-    __shared__ R sr[BP];
+    __shared__ unsigned long long sr[BP];
     const int t = blockIdx.x;
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
-    for (int k = threadIdx.x; k < BP; k += NT) sr[k] = R(0);
+    for (int k = threadIdx.x; k < BP; k += NT) sr[k] = 0ull;
     __syncthreads();
     for (int s = 0; s < d.nsp; ++s) {
         const SpDev<R> &P = d.sp[s];
@@ -822,15 +832,15 @@ __global__ __launch_bounds__(NT) void k_rho(SimDev<R> d)
             const int c = P.cell[base + p];
             const R x = P.x[base + p], y = P.y[base + p];
             const int k = (cell_x(c) - x0 + 1) + (cell_y(c) - y0 + 1) * PX;
-            lds_add(sr + k, P.qp * (R(1) - x) * (R(1) - y));
-            lds_add(sr + k + 1, P.qp * x * (R(1) - y));
-            lds_add(sr + k + PX, P.qp * (R(1) - x) * y);
-            lds_add(sr + k + PX + 1, P.qp * x * y);
+            lds_acc(sr + k, P.qp * (R(1) - x) * (R(1) - y), d.jq);
+            lds_acc(sr + k + 1, P.qp * x * (R(1) - y), d.jq);
+            lds_acc(sr + k + PX, P.qp * (R(1) - x) * y, d.jq);
+            lds_acc(sr + k + PX + 1, P.qp * x * y, d.jq);
         }
     }
     __syncthreads();
     R *out = d.blk + (size_t)t * 3 * BP;
-    for (int k = threadIdx.x; k < BP; k += NT) out[k] = sr[k];
+    for (int k = threadIdx.x; k < BP; k += NT) out[k] = (R)fx_value(sr[k], d.jq_inv);
 }
 
 template <typename R>
@@ -945,7 +955,7 @@ __global__ __launch_bounds__(NT) void k_diag_ke(SimDev<R> d)
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    load_tile_fields(d, d.st->parity, x0, y0, w, h, sf, (R *)nullptr);
+    load_tile_fields(d, d.st->parity, x0, y0, w, h, sf, (unsigned long long *)nullptr);
     __syncthreads();
     for (int s = 0; s < d.nsp; ++s) {
         const SpDev<R> &P = d.sp[s];
