@@ -156,7 +156,8 @@ int pic_init(const pic_cfg *cfg, void *arena, size_t arena_bytes, void *stream,
 /* Stages 1-3 plus the particle hand-off between tiles (hot-path rows a1-a4):
  * interpolate E^n, B^n to every particle, Boris push to u^{n+1/2}, move, and
  * deposit the Villasenor-Buneman current of the move into per-tile blocks;
- * then migrate the particles that left their tile.  Asynchronous on stream. */
+ * then append the particles that left their tile to the tile they entered.
+ * Asynchronous on stream. */
 int pic_deposit(pic_sim *sim, void *stream);
 
 /* Rows a5-a8: fold the per-tile current blocks into the global current
@@ -168,7 +169,9 @@ int pic_deposit(pic_sim *sim, void *stream);
  * Asynchronous on stream. */
 int pic_field_advance(pic_sim *sim, void *stream);
 
-/* nsteps times (pic_deposit; pic_field_advance).  After the first call the
+/* nsteps times (pic_deposit; pic_field_advance).  Between steps the leavers
+ * of a push stay in their outboxes and the next push takes them from there
+ * (calls that read particles append them first).  After the first call the
  * step is replayed from a captured HIP graph.  Asynchronous on stream. */
 int pic_step(pic_sim *sim, int nsteps, void *stream);
 
@@ -218,7 +221,7 @@ int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream);
  * of pic_deposit / pic_field_advance / pic_step (which then launch directly,
  * not from the graph).  pic_timing(sim, 1) resets and starts, 0 stops.
  * pic_timing_read fills ms[k] (summed milliseconds) and launches[k] for
- * k < nk of: 0 push+deposit, 1 migrate, 2 fold, 3 filter, 4 Yee,
+ * k < nk of: 0 push+deposit, 1 hand-off (settle), 2 fold, 3 filter, 4 Yee,
  * 5 window/step bookkeeping.  Synchronises. */
 #define PIC_NK 6
 int pic_timing(pic_sim *sim, int enable, void *stream);

@@ -92,7 +92,9 @@ int layout(const pic_cfg *c, Layout *L)
         L->cap[s] = (int)cap;
         maxcap = std::max(maxcap, (int)cap);
     }
-    L->cap_out = std::min(MAX_OUT, std::max(64, (maxcap / 8 + 63) / 64 * 64));
+    // outbox: 1/16 of the slots per tile (a leaver fraction far above what a
+    // particle moving at most one cell per step through a 16-cell tile gives)
+    L->cap_out = std::min(MAX_OUT, std::max(64, (maxcap / 16 + 63) / 64 * 64));
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -110,14 +112,16 @@ int layout(const pic_cfg *c, Layout *L)
     L->off_blk = take((size_t)L->ntiles * 3 * BP * L->rs);
     L->off_red = take(((size_t)NB_DIAG * 5 + (size_t)L->ntiles * MAX_SP) * 8);
     L->off_res = take(N_RED * 8);
+    const size_t obs = (size_t)L->ntiles * L->cap_out;
     for (int s = 0; s < c->n_species; ++s) {
         const size_t slots = (size_t)L->ntiles * L->cap[s];
-        const size_t obs = (size_t)L->ntiles * L->cap_out;
         size_t b = 0;
-        b += align256(slots * 4) + 5 * align256(slots * L->rs);  // particles
-        b += align256((size_t)L->ntiles * 4);                     // count
-        b += 2 * align256(obs * 4) + 5 * align256(obs * L->rs);   // outbox + holes
-        b += align256((size_t)L->ntiles * 4);                     // outbox count
+        // two particle buffers (packed cell + 5 components + per-tile count)
+        b += 2 * (align256(slots * 4) + 5 * align256(slots * L->rs) +
+                  align256((size_t)L->ntiles * 4));
+        // two outboxes (cell, direction byte, 5 components, per-tile count)
+        b += 2 * (align256(obs * 4) + align256(obs) + 5 * align256(obs * L->rs) +
+                  align256((size_t)L->ntiles * 4));
         L->off_sp[s] = take(b);
         L->sp_bytes[s] = b;
     }
@@ -193,21 +197,26 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
             q += align256(bytes);
             return r;
         };
-        P.cell = (int *)next(slots * 4);
-        P.x = (R *)next(slots * L.rs);
-        P.y = (R *)next(slots * L.rs);
-        P.ux = (R *)next(slots * L.rs);
-        P.uy = (R *)next(slots * L.rs);
-        P.uz = (R *)next(slots * L.rs);
-        P.count = (int *)next((size_t)L.ntiles * 4);
-        P.ob_cell = (int *)next(obs * 4);
-        P.ob_hole = (int *)next(obs * 4);
-        P.ob_x = (R *)next(obs * L.rs);
-        P.ob_y = (R *)next(obs * L.rs);
-        P.ob_ux = (R *)next(obs * L.rs);
-        P.ob_uy = (R *)next(obs * L.rs);
-        P.ob_uz = (R *)next(obs * L.rs);
-        P.ob_count = (int *)next((size_t)L.ntiles * 4);
+        for (int b = 0; b < 2; ++b) {
+            PartBuf<R> &B = P.pb[b];
+            B.cell = (int *)next(slots * 4);
+            B.x = (R *)next(slots * L.rs);
+            B.y = (R *)next(slots * L.rs);
+            B.ux = (R *)next(slots * L.rs);
+            B.uy = (R *)next(slots * L.rs);
+            B.uz = (R *)next(slots * L.rs);
+            B.count = (int *)next((size_t)L.ntiles * 4);
+        }
+        for (int b = 0; b < 2; ++b) {
+            P.ob_cell[b] = (int *)next(obs * 4);
+            P.ob_dir[b] = (unsigned char *)next(obs);
+            P.ob_x[b] = (R *)next(obs * L.rs);
+            P.ob_y[b] = (R *)next(obs * L.rs);
+            P.ob_ux[b] = (R *)next(obs * L.rs);
+            P.ob_uy[b] = (R *)next(obs * L.rs);
+            P.ob_uz[b] = (R *)next(obs * L.rs);
+            P.ob_count[b] = (int *)next((size_t)L.ntiles * 4);
+        }
         const double qp = (p.q_over_m < 0 ? -1.0 : 1.0) * p.density / (p.ppc_x * p.ppc_y);
         P.qm = (R)p.q_over_m;
         P.qp = (R)qp;
@@ -322,14 +331,24 @@ int timed(pic_sim *s, int kind, hipStream_t st, Fn fn)
     return PIC_OK;
 }
 
+// Append pending leavers to their tiles (no-op when none are pending).
+template <typename R>
+int enqueue_settle(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    return timed(s, 1, st, [&] { return Launch<R>::settle(d, st); });
+}
+
+// a1-a4: push + deposit; the leavers are then appended to their new tiles
 template <typename R>
 int enqueue_deposit(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
     int rc = timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
     if (rc) return rc;
-    return timed(s, 1, st, [&] { return Launch<R>::migrate(d, st); });
+    return enqueue_settle(s, d, st);
 }
 
+// a5-a8.  The window kernels need complete tiles, so leavers are settled
+// first with the moving window.
 template <typename R>
 int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
@@ -345,8 +364,22 @@ int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
     if (rc) return rc;
     rc = timed(s, 5, st, [&] { return Launch<R>::step_end(d, st); });
     if (rc) return rc;
-    if (d.window) rc = timed(s, 5, st, [&] { return Launch<R>::window(d, st); });
+    if (d.window) {
+        rc = enqueue_settle(s, d, st);
+        if (rc) return rc;
+        rc = timed(s, 5, st, [&] { return Launch<R>::window(d, st); });
+    }
     return rc;
+}
+
+// One step of pic_step: the next push takes the pending leavers directly
+// from the outboxes, so no hand-off launch is needed between steps.
+template <typename R>
+int enqueue_step(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    int rc = timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
+    if (rc) return rc;
+    return enqueue_field_advance(s, d, st);
 }
 
 // Charge density of the current particles: rho, and F rho in rho_f.
@@ -411,7 +444,9 @@ int do_init(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 template <typename R>
 int do_energy(pic_sim *s, const SimDev<R> &d, pic_diag *out, hipStream_t st)
 {
-    int rc = read_state(s, st);
+    int rc = enqueue_settle(s, d, st);
+    if (rc) return rc;
+    rc = read_state(s, st);
     if (rc) return rc;
     const int has_prev = s->rho_prev_iter == s->hs.iter - 1;
     rc = enqueue_rho(d, st);
@@ -424,8 +459,8 @@ int do_energy(pic_sim *s, const SimDev<R> &d, pic_diag *out, hipStream_t st)
     std::memset(out, 0, sizeof(*out));
     double charge = 0;
     for (int sp = 0; sp < d.nsp; ++sp) {
-        HIPCHK(hipMemcpyAsync(cnt.data(), d.sp[sp].count, cnt.size() * 4, hipMemcpyDeviceToHost,
-                              st));
+        HIPCHK(hipMemcpyAsync(cnt.data(), d.sp[sp].pb[s->hs.ppar].count, cnt.size() * 4,
+                              hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         long long n = 0;
         for (int v : cnt) n += v;
@@ -462,7 +497,9 @@ int do_set_particles(pic_sim *s, const SimDev<R> &d, int sp, long long n, const 
 {
     const pic_cfg &c = s->cfg;
     const Layout &L = s->L;
-    int rc = read_state(s, st);
+    int rc = enqueue_settle(s, d, st);
+    if (rc) return rc;
+    rc = read_state(s, st);
     if (rc) return rc;
     const int origin = s->hs.origin;
     std::vector<int> tile((size_t)n), cnt((size_t)L.ntiles, 0);
@@ -496,10 +533,11 @@ int do_set_particles(pic_sim *s, const SimDev<R> &d, int sp, long long n, const 
         huy[q] = (R)uy[k];
         huz[q] = (R)uz[k];
     }
-    const SpDev<R> &P = d.sp[sp];
+    const PartBuf<R> &P = d.sp[sp].pb[s->hs.ppar];
+    const int cap = d.sp[sp].cap;
     for (int t = 0; t < L.ntiles; ++t) {
         if (!cnt[t]) continue;
-        const size_t dst = (size_t)t * P.cap, src = (size_t)start[t], m = (size_t)cnt[t];
+        const size_t dst = (size_t)t * cap, src = (size_t)start[t], m = (size_t)cnt[t];
         HIPCHK(hipMemcpyAsync(P.cell + dst, hc.data() + src, m * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(P.x + dst, hx.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(P.y + dst, hy.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
@@ -518,9 +556,12 @@ int do_get_particles(pic_sim *s, const SimDev<R> &d, int sp, long long cap, long
                      hipStream_t st)
 {
     const Layout &L = s->L;
-    int rc = read_state(s, st);
+    int rc = enqueue_settle(s, d, st);
     if (rc) return rc;
-    const SpDev<R> &P = d.sp[sp];
+    rc = read_state(s, st);
+    if (rc) return rc;
+    const PartBuf<R> &P = d.sp[sp].pb[s->hs.ppar];
+    const int scap = d.sp[sp].cap;
     std::vector<int> cnt((size_t)L.ntiles);
     HIPCHK(hipMemcpyAsync(cnt.data(), P.count, cnt.size() * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -534,7 +575,7 @@ int do_get_particles(pic_sim *s, const SimDev<R> &d, int sp, long long cap, long
     long long q = 0;
     for (int t = 0; t < L.ntiles; ++t) {
         if (!cnt[t]) continue;
-        const size_t src = (size_t)t * P.cap, m = (size_t)cnt[t];
+        const size_t src = (size_t)t * scap, m = (size_t)cnt[t];
         HIPCHK(hipMemcpyAsync(hc.data() + q, P.cell + src, m * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hx.data() + q, P.x + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hy.data() + q, P.y + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
@@ -600,9 +641,7 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
 {
     if (s->timing) {
         for (int n = 0; n < nsteps; ++n) {
-            int rc = enqueue_deposit(s, d, st);
-            if (rc) return rc;
-            rc = enqueue_field_advance(s, d, st);
+            int rc = enqueue_step(s, d, st);
             if (rc) return rc;
         }
         return PIC_OK;
@@ -610,8 +649,7 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
     if (!s->gexec) {
         if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-        int rc = enqueue_deposit(s, d, s->cap_stream);
-        if (!rc) rc = enqueue_field_advance(s, d, s->cap_stream);
+        int rc = enqueue_step(s, d, s->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
         if (rc) return rc;

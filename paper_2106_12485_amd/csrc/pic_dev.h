@@ -27,7 +27,7 @@ constexpr int PY = TY + 3;
 constexpr int BP = PX * PY;         // cells of a tile block
 constexpr int NT = 256;             // threads per block (4 wavefronts)
 constexpr int MAX_SP = 4;
-constexpr int MAX_OUT = 4096;       // outbox slots per tile and species
+constexpr int MAX_OUT = 2048;       // outbox slots per tile and species
 constexpr int MAX_FR = 4;           // largest filter halo (passes + compensator)
 constexpr int QX = TX + 2 * MAX_FR; // LDS pitch of the filter block
 constexpr int QY = TY + 2 * MAX_FR;
@@ -44,18 +44,40 @@ struct DevState {
     int nshift;       // window shifts done
     int shift;        // 1 if the last step shifted the window
     int err;          // ERR_* bits
-    int pad;
+    int ppar;         // particle buffer holding the tiles' particles
+    int opar;         // outbox written by the last push
+    int pend;         // 1: that outbox holds leavers not yet in any tile
+};
+
+// Particle hand-off between tiles.  A push reads its tile from particle
+// buffer ppar, together with the leavers its 8 neighbours sent it in outbox
+// opar (if pending), and writes the particles that stay, compacted, to buffer
+// ppar ^ 1 and the ones that leave to outbox opar ^ 1, each tagged with the
+// direction (dx, dy) of its tile step; the neighbour in that direction picks
+// it up.  k_push_end then flips both parities and marks the new outbox
+// pending; k_settle appends pending leavers to their tiles when the particle
+// set must be complete (host reads, diagnostics, window shifts).
+constexpr int N_DIR = 8;
+__device__ __forceinline__ int dir_index(int dtx, int dty)
+{
+    const int k = (dtx + 1) + 3 * (dty + 1);  // 0..8 without the centre 4
+    return k < 4 ? k : k - 1;
+}
+
+template <typename R>
+struct PartBuf {
+    int *cell;        // packed storage cell: ix | iy << 16
+    R *x, *y, *ux, *uy, *uz;
+    int *count;       // particles per tile
 };
 
 template <typename R>
 struct SpDev {
-    int *cell;        // packed storage cell: ix | iy << 16 (-1 = removed)
-    R *x, *y, *ux, *uy, *uz;
-    int *count;       // live particles per tile
-    int *ob_cell;     // outbox of leavers: ntiles x cap_out
-    R *ob_x, *ob_y, *ob_ux, *ob_uy, *ob_uz;
-    int *ob_hole;     // slot each leaver left behind in its tile
-    int *ob_count;    // leavers (= holes) per tile
+    PartBuf<R> pb[2];                 // ping-pong particle buffers: ntiles x cap
+    int *ob_cell[2];                  // outboxes: ntiles x cap_out
+    R *ob_x[2], *ob_y[2], *ob_ux[2], *ob_uy[2], *ob_uz[2];
+    unsigned char *ob_dir[2];         // dir_index of each leaver's tile step
+    int *ob_count[2];                 // leavers per tile
     R qm, qp, tau;    // q/m, charge per particle, (dt/2)(q/m)
     int cap;          // slots per tile
     int ppc_x, ppc_y;
@@ -136,6 +158,12 @@ __device__ __forceinline__ T &at(T *base, unsigned byte_off)
     return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
 }
 
+template <typename T>
+__device__ __forceinline__ const T &at(const T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 __device__ __forceinline__ double fx_value(unsigned long long q, double jq_inv)
 {
     return (double)(long long)q * jq_inv;
@@ -162,7 +190,7 @@ __device__ __forceinline__ int window_col(int gx, int origin, int nxs)
 // Launchers (defined in pic_kernels.hip for R = float and double).
 template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
-    static hipError_t migrate(const SimDev<R> &d, hipStream_t s);
+    static hipError_t settle(const SimDev<R> &d, hipStream_t s);
     static hipError_t fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s);
     static hipError_t filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
                              const R *i2, R *o0, R *o1, R *o2, hipStream_t s);

@@ -162,53 +162,123 @@ __device__ __forceinline__ void load_tile_fields(const SimDev<R> &d, int par, in
     }
 }
 
+// Filled in by the first N_DIR threads of a block for species P: the 8
+// neighbour tiles of t, the direction a leaver of each must have to come to
+// t, and the exclusive prefix of their outbox lengths (outbox ob, or empty
+// runs when nothing is pending).  Returns nothing; needs a barrier after.
+template <typename R>
+__device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R> &P, int t,
+                                               int ob, bool pend, int *s_nb,
+                                               unsigned char *s_want, int *s_len)
+{
+    if (threadIdx.x < N_DIR) {
+        const int tx = t % d.ntx, ty = t / d.ntx;
+        const int k9 = threadIdx.x < 4 ? threadIdx.x : threadIdx.x + 1;
+        const int ox = k9 % 3 - 1, oy = k9 / 3 - 1;
+        const int nb = wrapi(tx + ox, d.ntx) + wrapi(ty + oy, d.nty) * d.ntx;
+        s_nb[threadIdx.x] = nb;
+        // particles that moved from nb into t stepped by (-ox, -oy)
+        s_want[threadIdx.x] = (unsigned char)dir_index(-ox, -oy);
+        s_len[threadIdx.x] = pend ? P.ob_count[ob][nb] : 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// rows a1-a3 (+ the leaver test of a4): one block per tile
+// rows a1-a4: one block per tile and step.  Every particle of the tile
+// (buffer ppar) and every leaver of the previous push that came to this tile
+// (outbox opar, if pending) is interpolated, pushed and deposited; particles
+// that stay are written compacted to buffer ppar ^ 1, one contiguous run per
+// wavefront, and the ones that leave go to outbox opar ^ 1 with their
+// direction.  Particles leaving the moving window are dropped.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
+__global__ __launch_bounds__(NT, 8) void k_push_deposit(SimDev<R> d)
 {
     __shared__ R sf[6 * BP];
     __shared__ unsigned long long sj[3 * BP];
-    __shared__ int s_nout;
+    __shared__ int s_nb[N_DIR], s_pre[N_DIR + 1];
+    __shared__ unsigned char s_want[N_DIR];
+    __shared__ int s_out, s_nob;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    const int par = d.st->parity;
-    const int origin = d.st->origin;
+    const DevState *st = d.st;
+    const int par = st->parity, origin = st->origin;
+    const int pp = st->ppar, ob = st->opar;
+    const bool pend = st->pend != 0;
     load_tile_fields(d, par, x0, y0, w, h, sf, sj);
-    if (threadIdx.x == 0) s_nout = 0;
-    __syncthreads();
 
     const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const R jq = d.jq;
+    const size_t obase = (size_t)t * d.cap_out;
     for (int s = 0; s < d.nsp; ++s) {
         const SpDev<R> &P = d.sp[s];
-        const unsigned n = (unsigned)P.count[t];
+        neighbour_runs(d, P, t, ob, pend, s_nb, s_want, s_pre + 1);
+        if (threadIdx.x == 0) {
+            s_out = 0;
+            s_nob = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_pre[0] = 0;
+            for (int k = 0; k < N_DIR; ++k) s_pre[k + 1] += s_pre[k];
+        }
+        __syncthreads();
+        const PartBuf<R> &bi = P.pb[pp];
+        const PartBuf<R> &bo = P.pb[pp ^ 1];
+        const unsigned n_own = (unsigned)bi.count[t];
+        const unsigned total = n_own + (unsigned)s_pre[N_DIR];
         const size_t base = (size_t)t * P.cap;
         // tile-uniform base pointers, indexed with 32-bit offsets
-        int *const pc = P.cell + base;
-        R *const px = P.x + base;
-        R *const py = P.y + base;
-        R *const pux = P.ux + base;
-        R *const puy = P.uy + base;
-        R *const puz = P.uz + base;
-        const size_t obase = (size_t)t * d.cap_out;
+        const int *const ic = bi.cell + base;
+        const R *const ixp = bi.x + base;
+        const R *const iyp = bi.y + base;
+        const R *const iux = bi.ux + base;
+        const R *const iuy = bi.uy + base;
+        const R *const iuz = bi.uz + base;
+        int *const oc = bo.cell + base;
+        R *const oxp = bo.x + base;
+        R *const oyp = bo.y + base;
+        R *const oux = bo.ux + base;
+        R *const ouy = bo.uy + base;
+        R *const ouz = bo.uz + base;
         const R qjx = P.qp * d.jxs, qjy = P.qp * d.jys;
         const R tau = P.tau;
-        for (unsigned p0 = 0; p0 < n; p0 += NT) {
+        for (unsigned p0 = 0; p0 < total; p0 += NT) {
             const unsigned p = p0 + threadIdx.x;
-            bool leave = false, dead = false;
-            int ncell = 0;
-            R xn = 0, yn = 0, ux = 0, uy = 0, uz = 0;
-            const unsigned o4 = p * 4u, oR = p * (unsigned)sizeof(R);
-            if (p < n) {
-                const int cell = at(pc, o4);
-                const R x = at(px, oR), y = at(py, oR);
-                ux = at(pux, oR);
-                uy = at(puy, oR);
-                uz = at(puz, oR);
+            bool act = false;
+            int cell = 0;
+            R x = 0, y = 0, ux = 0, uy = 0, uz = 0;
+            if (p < n_own) {
+                const unsigned o4 = p * 4u, oR = p * (unsigned)sizeof(R);
+                cell = at(ic, o4);
+                x = at(ixp, oR);
+                y = at(iyp, oR);
+                ux = at(iux, oR);
+                uy = at(iuy, oR);
+                uz = at(iuz, oR);
+                act = true;
+            } else if (p < total) {
+                const int e = (int)(p - n_own);
+                int k = 0;
+                while (k < N_DIR - 1 && e >= s_pre[k + 1]) ++k;
+                const size_t o = (size_t)s_nb[k] * d.cap_out + (e - s_pre[k]);
+                if (P.ob_dir[ob][o] == s_want[k]) {
+                    cell = P.ob_cell[ob][o];
+                    x = P.ob_x[ob][o];
+                    y = P.ob_y[ob][o];
+                    ux = P.ob_ux[ob][o];
+                    uy = P.ob_uy[ob][o];
+                    uz = P.ob_uz[ob][o];
+                    act = true;
+                }
+            }
+            bool stay = false, send = false;
+            int ncell = 0, dir = 0;
+            R xn = 0, yn = 0;
+            if (act) {
                 const int ix = cell_x(cell), iy = cell_y(cell);
                 const int lx = ix - x0, ly = iy - y0;
                 // stage 1: each component from its own staggered grid
@@ -248,36 +318,53 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
                 if (xn >= R(1)) { xn -= R(1); di += 1; }
                 if (yn >= R(1)) { yn -= R(1); dj += 1; }
                 const int nix = wrapi(ix + di, d.nxs), niy = wrapi(iy + dj, d.ny);
-                if (d.window) dead = window_col(nix, origin, d.nxs) >= d.nx;
+                const bool dead = d.window && window_col(nix, origin, d.nxs) >= d.nx;
+                // tile step; a tile that is the whole period wraps onto itself
+                const int dtx = d.ntx == 1 ? 0 : (lx + di >= w ? 1 : (lx + di < 0 ? -1 : 0));
+                const int dty = d.nty == 1 ? 0 : (ly + dj >= h ? 1 : (ly + dj < 0 ? -1 : 0));
                 ncell = pack_cell(nix, niy);
-                leave = dead || (nix / TX + (niy / TY) * d.ntx) != t;
-                if (!leave) {
-                    at(pc, o4) = ncell;
-                    at(px, oR) = xn;
-                    at(py, oR) = yn;
-                    at(pux, oR) = ux;
-                    at(puy, oR) = uy;
-                    at(puz, oR) = uz;
+                send = !dead && (dtx || dty);
+                stay = !dead && !send;
+                dir = dir_index(dtx, dty);
+            }
+            // stayers: one contiguous run per wavefront in buffer ppar ^ 1
+            const unsigned long long ms = __ballot(stay);
+            if (ms) {
+                int off = 0;
+                if (lane == 0) off = atomicAdd(&s_out, (int)__popcll(ms));
+                off = __shfl(off, 0);
+                if (stay) {
+                    const unsigned q = (unsigned)(off + (int)__popcll(ms & below));
+                    if (q < (unsigned)P.cap) {
+                        const unsigned o4 = q * 4u, oR = q * (unsigned)sizeof(R);
+                        at(oc, o4) = ncell;
+                        at(oxp, oR) = xn;
+                        at(oyp, oR) = yn;
+                        at(oux, oR) = ux;
+                        at(ouy, oR) = uy;
+                        at(ouz, oR) = uz;
+                    } else {
+                        atomicOr(&d.st->err, ERR_CAPACITY);
+                    }
                 }
             }
-            // row a4: wavefront ballot + prefix count gives each leaver its
-            // outbox slot; one LDS atomic per wavefront
-            const unsigned long long m = __ballot(leave);
-            if (m) {
+            // leavers: one contiguous run per wavefront in outbox opar ^ 1
+            const unsigned long long ml = __ballot(send);
+            if (ml) {
                 int off = 0;
-                if (lane == 0) off = atomicAdd(&s_nout, (int)__popcll(m));
+                if (lane == 0) off = atomicAdd(&s_nob, (int)__popcll(ml));
                 off = __shfl(off, 0);
-                if (leave) {
-                    const int slot = off + (int)__popcll(m & ((1ull << lane) - 1ull));
+                if (send) {
+                    const int slot = off + (int)__popcll(ml & below);
                     if (slot < d.cap_out) {
                         const size_t o = obase + slot;
-                        P.ob_hole[o] = (int)p;
-                        P.ob_cell[o] = dead ? -1 : ncell;
-                        P.ob_x[o] = xn;
-                        P.ob_y[o] = yn;
-                        P.ob_ux[o] = ux;
-                        P.ob_uy[o] = uy;
-                        P.ob_uz[o] = uz;
+                        P.ob_cell[ob ^ 1][o] = ncell;
+                        P.ob_dir[ob ^ 1][o] = (unsigned char)dir;
+                        P.ob_x[ob ^ 1][o] = xn;
+                        P.ob_y[ob ^ 1][o] = yn;
+                        P.ob_ux[ob ^ 1][o] = ux;
+                        P.ob_uy[ob ^ 1][o] = uy;
+                        P.ob_uz[ob ^ 1][o] = uz;
                     } else {
                         atomicOr(&d.st->err, ERR_CAPACITY);
                     }
@@ -286,8 +373,8 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            P.ob_count[t] = min(s_nout, d.cap_out);
-            s_nout = 0;
+            bo.count[t] = min(s_out, P.cap);
+            P.ob_count[ob ^ 1][t] = min(s_nob, d.cap_out);
         }
         __syncthreads();
     }
@@ -297,112 +384,80 @@ __global__ __launch_bounds__(NT) void k_push_deposit(SimDev<R> d)
     for (int k = threadIdx.x; k < 3 * BP; k += NT) out[k] = (R)fx_value(sj[k], jqi);
 }
 
-// ---------------------------------------------------------------------------
-// row a4: hand-off of leavers to the tile that now holds them.  One block per
-// (tile, species).  Incoming particles fill the holes below the new count
-// first, then append; if fewer arrive than left, live particles from the tail
-// move into the remaining holes.
-// ---------------------------------------------------------------------------
+// After each push: both buffers flip and its outbox is pending.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_migrate(SimDev<R> d)
+__global__ void k_push_end(SimDev<R> d)
 {
-    __shared__ int s_low[MAX_OUT];
-    __shared__ unsigned s_bits[MAX_OUT / 32];
-    __shared__ int s_nb[8];
-    __shared__ int s_nnb, s_in, s_nlow, s_ctr, s_ctr2;
-    const int t = blockIdx.x, s = blockIdx.y;
-    const SpDev<R> &P = d.sp[s];
-    const int tx = t % d.ntx, ty = t / d.ntx;
-    if (threadIdx.x == 0) {
-        int nn = 0;
-        for (int oy = -1; oy <= 1; ++oy)
-            for (int ox = -1; ox <= 1; ++ox) {
-                if (!ox && !oy) continue;
-                const int nb = wrapi(tx + ox, d.ntx) + wrapi(ty + oy, d.nty) * d.ntx;
-                bool dup = nb == t;
-                for (int k = 0; k < nn; ++k) dup |= s_nb[k] == nb;
-                if (!dup) s_nb[nn++] = nb;
+    if (threadIdx.x != 0) return;
+    DevState *st = d.st;
+    st->ppar ^= 1;
+    st->opar ^= 1;
+    st->pend = 1;
+}
+
+// Append the pending leavers (outbox opar) to the tiles they moved into, so
+// that buffer ppar holds every particle.  One wavefront per tile; ranks from
+// ballots, so the order is deterministic.  k_unpend then clears the flag.
+constexpr int MT = 64;
+
+template <typename R>
+__global__ __launch_bounds__(MT) void k_settle(SimDev<R> d)
+{
+    __shared__ int s_nb[N_DIR], s_len[N_DIR];
+    __shared__ unsigned char s_want[N_DIR];
+    const DevState *st = d.st;
+    if (!st->pend) return;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int pp = st->ppar, ob = st->opar;
+    const int lane = threadIdx.x;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int s = 0; s < d.nsp; ++s) {
+        const SpDev<R> &P = d.sp[s];
+        neighbour_runs(d, P, t, ob, true, s_nb, s_want, s_len);
+        __syncthreads();
+        int pre[N_DIR + 1];
+        pre[0] = 0;
+        for (int k = 0; k < N_DIR; ++k) pre[k + 1] = pre[k] + s_len[k];
+        const PartBuf<R> &B = P.pb[pp];
+        const int n0 = B.count[t];
+        const size_t base = (size_t)t * P.cap;
+        int added = 0;
+        for (int e0 = 0; e0 < pre[N_DIR]; e0 += MT) {
+            const int e = e0 + lane;
+            bool take = false;
+            size_t o = 0;
+            if (e < pre[N_DIR]) {
+                int k = 0;
+                while (k < N_DIR - 1 && e >= pre[k + 1]) ++k;
+                o = (size_t)s_nb[k] * d.cap_out + (e - pre[k]);
+                take = P.ob_dir[ob][o] == s_want[k];
             }
-        s_nnb = nn;
-        s_in = 0;
-        s_nlow = 0;
-        s_ctr = 0;
-        s_ctr2 = 0;
-    }
-    for (int k = threadIdx.x; k < MAX_OUT / 32; k += NT) s_bits[k] = 0u;
-    __syncthreads();
-    const int cap_out = d.cap_out;
-    // incoming count
-    int mine = 0;
-    for (int q = 0; q < s_nnb; ++q) {
-        const int nb = s_nb[q], no = P.ob_count[nb];
-        for (int k = threadIdx.x; k < no; k += NT) {
-            const int c = P.ob_cell[(size_t)nb * cap_out + k];
-            mine += (c >= 0 && cell_x(c) / TX + (cell_y(c) / TY) * d.ntx == t) ? 1 : 0;
-        }
-    }
-    if (mine) atomicAdd(&s_in, mine);
-    __syncthreads();
-    const int n_old = P.count[t], H = P.ob_count[t];
-    int I = s_in;
-    int n_new = n_old - H + I;
-    if (n_new > P.cap) {
-        I = P.cap - (n_old - H);
-        n_new = P.cap;
-        if (threadIdx.x == 0) atomicOr(&d.st->err, ERR_CAPACITY);
-    }
-    // holes below the new count are targets; holes at or above it are skipped
-    for (int k = threadIdx.x; k < H; k += NT) {
-        const int hp = P.ob_hole[(size_t)t * cap_out + k];
-        if (hp < n_new) {
-            s_low[atomicAdd(&s_nlow, 1)] = hp;
-        } else {
-            const int b = hp - n_new;
-            atomicOr(&s_bits[b >> 5], 1u << (b & 31));
-        }
-    }
-    __syncthreads();
-    const int h_low = s_nlow;
-    const size_t base = (size_t)t * P.cap;
-    for (int q = 0; q < s_nnb; ++q) {
-        const int nb = s_nb[q], no = P.ob_count[nb];
-        for (int k = threadIdx.x; k < no; k += NT) {
-            const size_t o = (size_t)nb * cap_out + k;
-            const int c = P.ob_cell[o];
-            if (c >= 0 && cell_x(c) / TX + (cell_y(c) / TY) * d.ntx == t) {
-                const int i = atomicAdd(&s_ctr, 1);
-                const int dl = i < h_low ? s_low[i] : n_old + (i - h_low);
-                if (i < I && dl < P.cap) {
-                    const size_t dst = base + dl;
-                    P.cell[dst] = c;
-                    P.x[dst] = P.ob_x[o];
-                    P.y[dst] = P.ob_y[o];
-                    P.ux[dst] = P.ob_ux[o];
-                    P.uy[dst] = P.ob_uy[o];
-                    P.uz[dst] = P.ob_uz[o];
+            const unsigned long long m = __ballot(take);
+            if (take) {
+                const int q = n0 + added + (int)__popcll(m & below);
+                if (q < P.cap) {
+                    const size_t dst = base + q;
+                    B.cell[dst] = P.ob_cell[ob][o];
+                    B.x[dst] = P.ob_x[ob][o];
+                    B.y[dst] = P.ob_y[ob][o];
+                    B.ux[dst] = P.ob_ux[ob][o];
+                    B.uy[dst] = P.ob_uy[ob][o];
+                    B.uz[dst] = P.ob_uz[ob][o];
+                } else {
+                    atomicOr(&d.st->err, ERR_CAPACITY);
                 }
             }
+            added += (int)__popcll(m);
         }
+        if (lane == 0) B.count[t] = min(n0 + added, P.cap);
+        __syncthreads();
     }
-    // live particles of the tail [n_new, n_old) fill the remaining low holes
-    for (int pos = n_new + threadIdx.x; pos < n_old; pos += NT) {
-        const int b = pos - n_new;
-        if (!((s_bits[b >> 5] >> (b & 31)) & 1u)) {
-            const int i = I + atomicAdd(&s_ctr2, 1);
-            if (i >= h_low) {  // the hole bookkeeping is inconsistent: flag, never write
-                atomicOr(&d.st->err, ERR_CAPACITY);
-                continue;
-            }
-            const size_t src = base + pos, dst = base + s_low[i];
-            P.cell[dst] = P.cell[src];
-            P.x[dst] = P.x[src];
-            P.y[dst] = P.y[src];
-            P.ux[dst] = P.ux[src];
-            P.uy[dst] = P.uy[src];
-            P.uz[dst] = P.uz[src];
-        }
-    }
-    if (threadIdx.x == 0) P.count[t] = n_new;
+}
+
+template <typename R>
+__global__ void k_unpend(SimDev<R> d)
+{
+    if (threadIdx.x == 0) d.st->pend = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -661,8 +716,9 @@ __global__ __launch_bounds__(NT) void k_window_clear(SimDev<R> d)
     }
     const int ty = blockIdx.x % d.nty, s = blockIdx.x / d.nty;
     const int t = col / TX + ty * d.ntx;
-    const SpDev<R> &P = d.sp[s];
-    const size_t base = (size_t)t * P.cap;
+    const SpDev<R> &S = d.sp[s];
+    const PartBuf<R> &P = S.pb[st->ppar];
+    const size_t base = (size_t)t * S.cap;
     const int n = P.count[t];
     int kept = 0;
     for (int p0 = 0; p0 < n; p0 += NT) {
@@ -708,11 +764,13 @@ __global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
     const int ty = blockIdx.x % d.nty, s = blockIdx.x / d.nty;
     const int t = col / TX + ty * d.ntx;
     const int y0 = ty * TY, h = min(TY, d.ny - y0);
-    const SpDev<R> &P = d.sp[s];
-    if (!(P.density > 0.0)) return;
-    const size_t base = (size_t)t * P.cap;
+    const SpDev<R> &S = d.sp[s];
+    if (!(S.density > 0.0)) return;
+    const PartBuf<R> &P = S.pb[st->ppar];
+    const int cap = S.cap;
+    const size_t base = (size_t)t * cap;
     const int n0 = P.count[t];
-    const int ppc = P.ppc_x * P.ppc_y;
+    const int ppc = S.ppc_x * S.ppc_y;
     const int total = h * ppc;
     int added = 0;
     for (int q0 = 0; q0 < total; q0 += NT) {
@@ -722,24 +780,24 @@ __global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
         if (q < total) {
             const int sub = q / h;
             j = y0 + q % h;
-            m = sub % P.ppc_x;
-            l = sub / P.ppc_x;
-            const double xo = ((double)m + 0.5) / (double)P.ppc_x;
+            m = sub % S.ppc_x;
+            l = sub / S.ppc_x;
+            const double xo = ((double)m + 0.5) / (double)S.ppc_x;
             const double xlab = ((double)ilab + xo) * d.dx_d;
-            ok = xlab >= P.x_lo && xlab < P.x_hi;
+            ok = xlab >= S.x_lo && xlab < S.x_hi;
         }
         int tot;
         const int r = block_rank(ok, s_w, &tot);
         if (ok) {
             const int pos = n0 + added + r;
-            if (pos < P.cap) {
+            if (pos < cap) {
                 R u[3];
-                maxwellian(P, d.key0, d.key1, (uint32_t)ilab, (uint32_t)j,
-                           (uint32_t)(l * P.ppc_x + m), (uint32_t)s, u);
+                maxwellian(S, d.key0, d.key1, (uint32_t)ilab, (uint32_t)j,
+                           (uint32_t)(l * S.ppc_x + m), (uint32_t)s, u);
                 const size_t o = base + pos;
                 P.cell[o] = pack_cell(col, j);
-                P.x[o] = (R)(((double)m + 0.5) / (double)P.ppc_x);
-                P.y[o] = (R)(((double)l + 0.5) / (double)P.ppc_y);
+                P.x[o] = (R)(((double)m + 0.5) / (double)S.ppc_x);
+                P.y[o] = (R)(((double)l + 0.5) / (double)S.ppc_y);
                 P.ux[o] = u[0];
                 P.uy[o] = u[1];
                 P.uz[o] = u[2];
@@ -749,7 +807,7 @@ __global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
         }
         added += tot;
     }
-    if (threadIdx.x == 0) P.count[t] = min(n0 + added, P.cap);
+    if (threadIdx.x == 0) P.count[t] = min(n0 + added, cap);
 }
 
 // Initial load of species s, one block per tile.  Particles are stored
@@ -763,10 +821,12 @@ __global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    const SpDev<R> &P = d.sp[s];
+    const SpDev<R> &S = d.sp[s];
+    const PartBuf<R> &P = S.pb[d.st->ppar];
     const int origin = d.st->origin, nshift = d.st->nshift;
-    const size_t base = (size_t)t * P.cap;
-    const int ncell = w * h, ppc = P.ppc_x * P.ppc_y;
+    const int cap = S.cap;
+    const size_t base = (size_t)t * cap;
+    const int ncell = w * h, ppc = S.ppc_x * S.ppc_y;
     const int total = ncell * ppc;
     int added = 0;
     for (int q0 = 0; q0 < total; q0 += NT) {
@@ -774,30 +834,30 @@ __global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
         bool ok = false;
         int gx = 0, gy = 0, m = 0, l = 0;
         long long ilab = 0;
-        if (q < total && P.density > 0.0) {
+        if (q < total && S.density > 0.0) {
             const int sub = q / ncell, c = q % ncell;
             gx = x0 + c % w;
             gy = y0 + c / w;
-            m = sub % P.ppc_x;
-            l = sub / P.ppc_x;
+            m = sub % S.ppc_x;
+            l = sub / S.ppc_x;
             const int wc = d.window ? window_col(gx, origin, d.nxs) : gx;
             ilab = (long long)wc + nshift;
-            const double xo = ((double)m + 0.5) / (double)P.ppc_x;
+            const double xo = ((double)m + 0.5) / (double)S.ppc_x;
             const double xlab = ((double)ilab + xo) * d.dx_d;
-            ok = wc < d.nx && xlab >= P.x_lo && xlab < P.x_hi;
+            ok = wc < d.nx && xlab >= S.x_lo && xlab < S.x_hi;
         }
         int tot;
         const int r = block_rank(ok, s_w, &tot);
         if (ok) {
             const int pos = added + r;
-            if (pos < P.cap) {
+            if (pos < cap) {
                 R u[3];
-                maxwellian(P, d.key0, d.key1, (uint32_t)ilab, (uint32_t)gy,
-                           (uint32_t)(l * P.ppc_x + m), (uint32_t)s, u);
+                maxwellian(S, d.key0, d.key1, (uint32_t)ilab, (uint32_t)gy,
+                           (uint32_t)(l * S.ppc_x + m), (uint32_t)s, u);
                 const size_t o = base + pos;
                 P.cell[o] = pack_cell(gx, gy);
-                P.x[o] = (R)(((double)m + 0.5) / (double)P.ppc_x);
-                P.y[o] = (R)(((double)l + 0.5) / (double)P.ppc_y);
+                P.x[o] = (R)(((double)m + 0.5) / (double)S.ppc_x);
+                P.y[o] = (R)(((double)l + 0.5) / (double)S.ppc_y);
                 P.ux[o] = u[0];
                 P.uy[o] = u[1];
                 P.uz[o] = u[2];
@@ -807,7 +867,7 @@ __global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
         }
         added += tot;
     }
-    if (threadIdx.x == 0) P.count[t] = min(added, P.cap);
+    if (threadIdx.x == 0) P.count[t] = min(added, cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -825,17 +885,19 @@ __global__ __launch_bounds__(NT) void k_rho(SimDev<R> d)
     for (int k = threadIdx.x; k < BP; k += NT) sr[k] = 0ull;
     __syncthreads();
     for (int s = 0; s < d.nsp; ++s) {
-        const SpDev<R> &P = d.sp[s];
+        const SpDev<R> &S = d.sp[s];
+        const PartBuf<R> &P = S.pb[d.st->ppar];
         const int n = P.count[t];
-        const size_t base = (size_t)t * P.cap;
+        const size_t base = (size_t)t * S.cap;
+        const R qp = S.qp;
         for (int p = threadIdx.x; p < n; p += NT) {
             const int c = P.cell[base + p];
             const R x = P.x[base + p], y = P.y[base + p];
             const int k = (cell_x(c) - x0 + 1) + (cell_y(c) - y0 + 1) * PX;
-            lds_acc(sr + k, P.qp * (R(1) - x) * (R(1) - y), d.jq);
-            lds_acc(sr + k + 1, P.qp * x * (R(1) - y), d.jq);
-            lds_acc(sr + k + PX, P.qp * (R(1) - x) * y, d.jq);
-            lds_acc(sr + k + PX + 1, P.qp * x * y, d.jq);
+            lds_acc(sr + k, qp * (R(1) - x) * (R(1) - y), d.jq);
+            lds_acc(sr + k + 1, qp * x * (R(1) - y), d.jq);
+            lds_acc(sr + k + PX, qp * (R(1) - x) * y, d.jq);
+            lds_acc(sr + k + PX + 1, qp * x * y, d.jq);
         }
     }
     __syncthreads();
@@ -958,10 +1020,11 @@ __global__ __launch_bounds__(NT) void k_diag_ke(SimDev<R> d)
     load_tile_fields(d, d.st->parity, x0, y0, w, h, sf, (unsigned long long *)nullptr);
     __syncthreads();
     for (int s = 0; s < d.nsp; ++s) {
-        const SpDev<R> &P = d.sp[s];
+        const SpDev<R> &S = d.sp[s];
+        const PartBuf<R> &P = S.pb[d.st->ppar];
         const int n = P.count[t];
-        const size_t base = (size_t)t * P.cap;
-        const double mp = (double)P.qp / (double)P.qm;
+        const size_t base = (size_t)t * S.cap;
+        const double mp = (double)S.qp / (double)S.qm;
         double ke = 0;
         for (int p = threadIdx.x; p < n; p += NT) {
             const int c = P.cell[base + p];
@@ -973,7 +1036,7 @@ __global__ __launch_bounds__(NT) void k_diag_ke(SimDev<R> d)
             const double ex = lerp2(sf, ixh, ly, wxh, y);
             const double ey = lerp2(sf + BP, lx, iyh, x, wyh);
             const double ez = lerp2(sf + 2 * BP, lx, ly, x, y);
-            const double tau = (double)P.tau;
+            const double tau = (double)S.tau;
             const double a = (double)P.ux[base + p] + tau * ex;
             const double b = (double)P.uy[base + p] + tau * ey;
             const double cc = (double)P.uz[base + p] + tau * ez;
@@ -1036,14 +1099,21 @@ template <typename R>
 hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_push_end<R>, dim3(1), dim3(64), 0, s, d);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t Launch<R>::migrate(const SimDev<R> &d, hipStream_t s)
+hipError_t Launch<R>::settle(const SimDev<R> &d, hipStream_t s)
 {
-    if (d.nsp == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_migrate<R>, dim3(d.ntiles, d.nsp), dim3(NT), 0, s, d);
+    if (d.nsp > 0) {
+        hipLaunchKernelGGL(k_settle<R>, dim3(d.ntiles), dim3(MT), 0, s, d);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_unpend<R>, dim3(1), dim3(64), 0, s, d);
     return hipGetLastError();
 }
 
