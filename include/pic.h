@@ -232,6 +232,70 @@ int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void 
  * particle slots per tile of species 0, out[6] outbox slots per tile. */
 int pic_layout(const pic_sim *sim, long long *out, int n);
 
+/* ---------------------------------------------------------------------
+ * Batches and serving.  Independent simulations resident on one GPU are
+ * stepped together: each kernel of a step is launched once for the tiles of
+ * every simulation of the batch (a device-side descriptor table and
+ * (simulation, tile) work list; the step is replayed from a captured HIP
+ * graph that serves every batch fitting its grid).  The cycle of each
+ * simulation is the one of pic_step; current sums are integers, so a
+ * simulation evolves bitwise identically alone and in any batch.
+ * ------------------------------------------------------------------- */
+typedef struct pic_batch pic_batch;
+
+/* Device workspace for a batch of up to max_sims FP32 periodic simulations
+ * (no moving window) with at most max_tiles tiles in total. */
+size_t pic_batch_mem_bytes(int max_sims, long long max_tiles);
+
+/* Lay a batch object out in `arena` (device memory owned by the caller, at
+ * least pic_batch_mem_bytes, 256-byte aligned).  Also uses pinned host
+ * staging for the descriptor table. */
+int pic_batch_create(void *arena, size_t arena_bytes, int max_sims, long long max_tiles,
+                     pic_batch **out);
+
+/* Step the n simulations `sims` together nsteps times on `stream`.  The set
+ * may change from call to call (simulations join and leave between calls);
+ * a change synchronises the stream once to restage the descriptors.  No
+ * simulation of the set may be stepped elsewhere meanwhile.  PIC_E_ARG for
+ * FP64 or moving-window simulations or a set that exceeds the batch. */
+int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *stream);
+
+int pic_batch_free(pic_batch *b);
+
+/* One serving request: a simulation, the steps to run, its arrival time in
+ * seconds after the start of pic_serve. */
+typedef struct {
+    pic_cfg cfg;
+    int nsteps;
+    double arrival_s;
+} pic_request;
+
+typedef struct {
+    double admit_s;      /* when it got memory and was initialised */
+    double done_s;       /* when its last step finished */
+    pic_diag diag;       /* diagnostics after the last step */
+    int status;          /* PIC_OK or the error that ended it */
+} pic_result;
+
+typedef struct {
+    int batched;         /* 1: continuous batching; 0: one at a time, in order */
+    int chunk_steps;     /* steps between admission points (>= 1) */
+    int max_batch;       /* most simulations stepped together (<= 0: 256) */
+    int diag_every;      /* unused if 0; else pic_energy each that many steps */
+} pic_serve_opts;
+
+/* Serve n requests in real time: a request is queued at its arrival time,
+ * admitted (first fit, in arrival order) when its pic_mem_bytes fits in the
+ * free part of `arena` (the HBM budget), initialised on a second stream while
+ * the batch keeps running, stepped with the batch in chunks of at most
+ * chunk_steps, and retired when done, freeing its memory.  out[i] receives
+ * request i's times and final diagnostics.  step_ms (capacity cap_steps,
+ * may be NULL) receives the time per batched step of every chunk and
+ * *n_steps their number.  Returns PIC_OK or the first host-side error. */
+int pic_serve(const pic_request *reqs, int n, void *arena, size_t arena_bytes,
+              const pic_serve_opts *opts, pic_result *out, double *step_ms,
+              long long cap_steps, long long *n_steps, void *stream);
+
 const char *pic_strerror(int code);
 const char *pic_last_error(void);
 

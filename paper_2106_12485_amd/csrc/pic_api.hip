@@ -5,7 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <map>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -269,7 +273,12 @@ struct pic_sim {
     // diagnostics
     long long rho_prev_iter = -2;
     DevState hs;  // host copy, valid after read_state
+    unsigned long long uid = 0;  // unique per pic_init (handles may reuse addresses)
 };
+
+namespace {
+std::atomic<unsigned long long> g_next_uid{1};
+}
 
 namespace {
 
@@ -688,6 +697,7 @@ int pic_init(const pic_cfg *cfg, void *arena, size_t arena_bytes, void *stream, 
         return fail(PIC_E_NOMEM, "arena holds " + std::to_string(arena_bytes) + " bytes, needs " +
                                      std::to_string(L.total));
     pic_sim *s = new pic_sim();
+    s->uid = g_next_uid.fetch_add(1);
     s->cfg = *cfg;
     s->L = L;
     s->arena = (char *)arena;
@@ -899,3 +909,344 @@ const char *pic_strerror(int code)
 const char *pic_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ===========================================================================
+// batches of simulations
+// ===========================================================================
+struct pic_batch {
+    char *arena = nullptr;
+    int max_sims = 0;
+    long long max_tiles = 0;
+    SimDev<float> *d_table = nullptr;
+    BatchDev *d_batch = nullptr;
+    int2 *d_work = nullptr;
+    SimDev<float> *h_table = nullptr;  // pinned staging
+    BatchDev *h_batch = nullptr;
+    int2 *h_work = nullptr;
+    std::vector<unsigned long long> cur;  // uids of the staged simulations
+    int grid = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+void batch_layout(int max_sims, long long max_tiles, size_t *o_table, size_t *o_batch,
+                  size_t *o_work, size_t *total)
+{
+    size_t o = 0;
+    *o_table = o;
+    o = align256(o + (size_t)max_sims * sizeof(SimDev<float>));
+    *o_batch = o;
+    o = align256(o + sizeof(BatchDev));
+    *o_work = o;
+    o = align256(o + (size_t)max_tiles * sizeof(int2));
+    *total = o;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pic_batch_mem_bytes(int max_sims, long long max_tiles)
+{
+    if (max_sims < 1 || max_tiles < 1) return 0;
+    size_t a, b, c, t;
+    batch_layout(max_sims, max_tiles, &a, &b, &c, &t);
+    return t;
+}
+
+int pic_batch_free(pic_batch *b)
+{
+    if (!b) return PIC_OK;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->h_table) (void)hipHostFree(b->h_table);
+    if (b->h_batch) (void)hipHostFree(b->h_batch);
+    if (b->h_work) (void)hipHostFree(b->h_work);
+    delete b;
+    return PIC_OK;
+}
+
+int pic_batch_create(void *arena, size_t arena_bytes, int max_sims, long long max_tiles,
+                     pic_batch **out)
+{
+    if (!out) return fail(PIC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!arena || ((uintptr_t)arena & 255) || max_sims < 1 || max_tiles < 1)
+        return fail(PIC_E_ARG, "bad batch arena or sizes");
+    size_t ot, ob, ow, total;
+    batch_layout(max_sims, max_tiles, &ot, &ob, &ow, &total);
+    if (arena_bytes < total) return fail(PIC_E_NOMEM, "batch arena too small");
+    pic_batch *b = new pic_batch();
+    b->arena = (char *)arena;
+    b->max_sims = max_sims;
+    b->max_tiles = max_tiles;
+    b->d_table = (SimDev<float> *)(b->arena + ot);
+    b->d_batch = (BatchDev *)(b->arena + ob);
+    b->d_work = (int2 *)(b->arena + ow);
+    hipError_t e = hipHostMalloc((void **)&b->h_table, (size_t)max_sims * sizeof(SimDev<float>));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_batch, sizeof(BatchDev));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_work, (size_t)max_tiles * sizeof(int2));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        pic_batch_free(b);
+        return fail(PIC_E_HIP, std::string("batch set-up: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *stream)
+{
+    if (!b || n < 0 || nsteps < 0 || (n > 0 && !sims)) return fail(PIC_E_ARG, "bad batch call");
+    if (n == 0 || nsteps == 0) return PIC_OK;
+    if (n > b->max_sims) return fail(PIC_E_ARG, "more simulations than the batch holds");
+    hipStream_t st = (hipStream_t)stream;
+    bool same = (int)b->cur.size() == n;
+    for (int i = 0; same && i < n; ++i) same = sims[i] && sims[i]->uid == b->cur[i];
+    if (!same) {
+        long long nwork = 0;
+        for (int i = 0; i < n; ++i) {
+            const pic_sim *s = sims[i];
+            if (!s || s->cfg.fp64 || s->cfg.moving_window)
+                return fail(PIC_E_ARG, "batches hold FP32 periodic simulations only");
+            nwork += s->L.ntiles;
+        }
+        if (nwork > b->max_tiles) return fail(PIC_E_ARG, "batch work list too long");
+        // the staging buffers may still feed an earlier copy
+        HIPCHK(hipStreamSynchronize(st));
+        long long w = 0;
+        for (int i = 0; i < n; ++i) {
+            b->h_table[i] = sims[i]->df;
+            for (int t = 0; t < sims[i]->L.ntiles; ++t) b->h_work[w++] = make_int2(i, t);
+        }
+        b->h_batch->nwork = (int)nwork;
+        b->h_batch->nsim = n;
+        b->h_batch->work = b->d_work;
+        HIPCHK(hipMemcpyAsync(b->d_table, b->h_table, (size_t)n * sizeof(SimDev<float>),
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(b->d_work, b->h_work, (size_t)nwork * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(b->d_batch, b->h_batch, sizeof(BatchDev), hipMemcpyHostToDevice,
+                              st));
+        b->cur.resize(n);
+        for (int i = 0; i < n; ++i) b->cur[i] = sims[i]->uid;
+        // one graph serves every work list up to its grid; blocks past the
+        // work count exit at once
+        const int need = (int)((nwork + 1023) / 1024 * 1024);
+        if (!b->gexec || need > b->grid || b->grid > 4 * need) {
+            if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->gexec = nullptr;
+            b->graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+            hipError_t le = launch_batch_step<float>(b->d_table, b->d_batch, need, b->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+            if (le != hipSuccess || ce != hipSuccess)
+                return fail(PIC_E_HIP, "batch graph capture failed");
+            b->graph = g;
+            HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+            b->grid = need;
+        }
+    }
+    for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(b->gexec, st));
+    return PIC_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// serving loop
+// ===========================================================================
+namespace {
+
+// First-fit allocator of 256-byte aligned ranges of the serving arena.
+class ArenaAlloc {
+  public:
+    explicit ArenaAlloc(size_t bytes) { free_[0] = bytes & ~(size_t)255; }
+    long long take(size_t bytes)
+    {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, left = it->second - bytes;
+                free_.erase(it);
+                if (left) free_[off + bytes] = left;
+                return (long long)off;
+            }
+        }
+        return -1;
+    }
+    void give(size_t off, size_t bytes)
+    {
+        bytes = align256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Active {
+    int req;
+    pic_sim *sim;
+    size_t off, bytes;
+    int left;
+};
+
+}  // namespace
+
+extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t arena_bytes,
+                         const pic_serve_opts *opts, pic_result *out, double *step_ms,
+                         long long cap_steps, long long *n_steps, void *stream)
+{
+    if (n < 0 || (n > 0 && (!reqs || !out)) || !arena || !opts || ((uintptr_t)arena & 255))
+        return fail(PIC_E_ARG, "bad serving arguments");
+    const int chunk = std::max(1, opts->chunk_steps);
+    const int max_batch = opts->batched ? (opts->max_batch > 0 ? opts->max_batch : 256) : 1;
+    if (n_steps) *n_steps = 0;
+    for (int i = 0; i < n; ++i) {
+        std::memset(&out[i], 0, sizeof(out[i]));
+        out[i].status = PIC_E_STATE;
+    }
+    // batch workspace at the start of the arena, the rest is the budget
+    long long max_tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        Layout L;
+        if (layout(&reqs[i].cfg, &L) == PIC_OK) max_tiles += L.ntiles;
+    }
+    max_tiles = std::max(1LL, std::min(max_tiles, 1LL << 22));
+    const size_t bws = pic_batch_mem_bytes(max_batch, max_tiles);
+    if (arena_bytes < bws) return fail(PIC_E_NOMEM, "budget smaller than the batch workspace");
+    pic_batch *batch = nullptr;
+    int rc = pic_batch_create(arena, bws, max_batch, max_tiles, &batch);
+    if (rc) return rc;
+    char *pool = (char *)arena + bws;
+    ArenaAlloc alloc(arena_bytes - bws);
+    hipStream_t sa = (hipStream_t)stream, sb = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        pic_batch_free(batch);
+        return fail(PIC_E_HIP, std::string("serving set-up: ") + hipGetErrorString(he));
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now = [&] {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    };
+    std::vector<int> queue;
+    std::vector<Active> active;
+    std::vector<pic_sim *> sims;
+    int next = 0, done = 0;
+    long long ns = 0;
+    rc = PIC_OK;
+    while (done < n && rc == PIC_OK) {
+        const double tnow = now();
+        while (next < n && reqs[order[next]].arrival_s <= tnow) queue.push_back(order[next++]);
+        // launch a chunk for the running set
+        int k = 0;
+        if (!active.empty()) {
+            k = chunk;
+            for (const Active &a : active) k = std::min(k, a.left);
+            sims.clear();
+            for (const Active &a : active) sims.push_back(a.sim);
+            (void)hipEventRecord(e0, sa);
+            rc = opts->batched ? pic_batch_step(batch, sims.data(), (int)sims.size(), k, sa)
+                               : pic_step(active[0].sim, k, sa);
+            (void)hipEventRecord(e1, sa);
+            if (rc) break;
+        }
+        // admit while the chunk runs: first fit in arrival order
+        for (size_t qi = 0; qi < queue.size() && (int)active.size() < max_batch;) {
+            if (!opts->batched && !active.empty()) break;
+            const int r = queue[qi];
+            const size_t need = pic_mem_bytes(&reqs[r].cfg);
+            if (need == 0) {
+                out[r].status = PIC_E_ARG;
+                ++done;
+                queue.erase(queue.begin() + qi);
+                continue;
+            }
+            const long long off = alloc.take(need);
+            if (off < 0) {
+                ++qi;
+                continue;
+            }
+            pic_sim *sim = nullptr;
+            const int ir = pic_init(&reqs[r].cfg, pool + off, need, sb, &sim);
+            queue.erase(queue.begin() + qi);
+            if (ir) {
+                alloc.give((size_t)off, need);
+                out[r].status = ir;
+                ++done;
+                continue;
+            }
+            out[r].admit_s = now();
+            active.push_back(Active{r, sim, (size_t)off, need, reqs[r].nsteps});
+            if (reqs[r].nsteps <= 0) active.back().left = 0;
+        }
+        if (k > 0) {
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (step_ms && ns < cap_steps) step_ms[ns] = ms / k;
+            ++ns;
+            for (Active &a : active)
+                if (a.sim != nullptr && std::find(sims.begin(), sims.end(), a.sim) != sims.end())
+                    a.left -= k;
+        }
+        // retire the finished ones
+        for (size_t ai = 0; ai < active.size();) {
+            Active &a = active[ai];
+            if (a.left > 0) {
+                ++ai;
+                continue;
+            }
+            out[a.req].status = pic_energy(a.sim, &out[a.req].diag, sa);
+            out[a.req].done_s = now();
+            pic_free(a.sim);
+            alloc.give(a.off, a.bytes);
+            ++done;
+            active.erase(active.begin() + ai);
+        }
+        if (active.empty() && queue.empty() && next < n) {
+            const double wait = reqs[order[next]].arrival_s - now();
+            if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+        } else if (active.empty() && !queue.empty() && k == 0) {
+            // nothing fits although nothing runs: the request exceeds the budget
+            const int r = queue.front();
+            out[r].status = PIC_E_NOMEM;
+            queue.erase(queue.begin());
+            ++done;
+        }
+    }
+    for (Active &a : active) pic_free(a.sim);
+    if (n_steps) *n_steps = ns;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(sb);
+    pic_batch_free(batch);
+    return rc;
+}

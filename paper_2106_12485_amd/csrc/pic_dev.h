@@ -187,6 +187,16 @@ __device__ __forceinline__ int window_col(int gx, int origin, int nxs)
     return w < 0 ? w + nxs : w;
 }
 
+// A batch of simulations stepped by shared launches: the kernels read the
+// work list (simulation, tile) and a descriptor table from device memory.
+struct BatchDev {
+    int nwork;        // entries of the work list in use
+    int nsim;         // descriptors in use
+    const int2 *work; // (simulation, tile), simulations in contiguous runs
+};
+template <typename R>
+hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s);
+
 // Launchers (defined in pic_kernels.hip for R = float and double).
 template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);

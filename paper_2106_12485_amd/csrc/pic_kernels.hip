@@ -192,14 +192,13 @@ __device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R
 // direction.  Particles leaving the moving window are dropped.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(NT, 8) void k_push_deposit(SimDev<R> d)
+__device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
 {
     __shared__ R sf[6 * BP];
     __shared__ unsigned long long sj[3 * BP];
     __shared__ int s_nb[N_DIR], s_pre[N_DIR + 1];
     __shared__ unsigned char s_want[N_DIR];
     __shared__ int s_out, s_nob;
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
@@ -386,9 +385,8 @@ __global__ __launch_bounds__(NT, 8) void k_push_deposit(SimDev<R> d)
 
 // After each push: both buffers flip and its outbox is pending.
 template <typename R>
-__global__ void k_push_end(SimDev<R> d)
+__device__ __forceinline__ void push_end_body(const SimDev<R> &d)
 {
-    if (threadIdx.x != 0) return;
     DevState *st = d.st;
     st->ppar ^= 1;
     st->opar ^= 1;
@@ -467,9 +465,9 @@ __global__ void k_unpend(SimDev<R> d)
 // beyond the window is dropped).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(NT) void k_fold(SimDev<R> d, int nplanes, R *o0, R *o1, R *o2)
+__device__ __forceinline__ void fold_body(const SimDev<R> &d, const int t, int nplanes, R *o0,
+                                          R *o1, R *o2)
 {
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
@@ -513,13 +511,13 @@ __global__ __launch_bounds__(NT) void k_fold(SimDev<R> d, int nplanes, R *o0, R 
 // then the y passes, keeping the gap at zero; write the interior.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(NT) void k_filter(SimDev<R> d, int nplanes, const R *i0,
-                                               const R *i1, const R *i2, R *o0, R *o1, R *o2)
+__device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int nplanes,
+                                            const R *i0, const R *i1, const R *i2, R *o0,
+                                            R *o1, R *o2)
 {
     __shared__ R sa[QX * QY];
     __shared__ R sb[QX * QY];
     __shared__ unsigned char s_gap[QX];
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
@@ -593,13 +591,12 @@ __global__ __launch_bounds__(NT) void k_filter(SimDev<R> d, int nplanes, const R
 // component is held at zero after each sub-step, as zero guard cells would.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(NT) void k_yee(SimDev<R> d)
+__device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
 {
     __shared__ R e[3 * BP];
     __shared__ R b[3 * BP];
     __shared__ R jl[3 * BP];
     __shared__ unsigned char s_gap[PX];
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
@@ -681,9 +678,8 @@ __global__ __launch_bounds__(NT) void k_yee(SimDev<R> d)
 // shift (the window advances one cell once iter*dt >= (nshift+1)*dx, in double)
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_step_end(SimDev<R> d)
+__device__ __forceinline__ void step_end_body(const SimDev<R> &d)
 {
-    if (threadIdx.x != 0) return;
     DevState *st = d.st;
     st->parity ^= 1;
     st->iter += 1;
@@ -1093,6 +1089,111 @@ __global__ void k_copy(const R *src, R *dst, long long n)
 }
 
 // ---------------------------------------------------------------------------
+// kernels of one step: one simulation (descriptor in the kernel arguments,
+// one block per tile), or a batch of simulations (descriptor table and a
+// (simulation, tile) work list in device memory; blocks past the work count
+// exit, so one captured graph serves every batch that fits its grid)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool batch_item(const BatchDev *__restrict__ b, int2 *item)
+{
+    const int nw = __builtin_amdgcn_readfirstlane(b->nwork);
+    if ((int)blockIdx.x >= nw) return false;
+    const int2 w = b->work[xcd_remap(blockIdx.x, nw)];
+    // block-uniform: keep the descriptor address in scalar registers
+    item->x = __builtin_amdgcn_readfirstlane(w.x);
+    item->y = __builtin_amdgcn_readfirstlane(w.y);
+    return true;
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT, 8) void k_push_deposit(SimDev<R> d)
+{
+    push_body(d, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_push_deposit_b(const SimDev<R> *__restrict__ ds,
+                                             const BatchDev *__restrict__ b)
+{
+    int2 it;
+    if (batch_item(b, &it)) push_body(ds[it.x], it.y);
+}
+
+template <typename R>
+__global__ void k_push_end(SimDev<R> d)
+{
+    if (threadIdx.x == 0) push_end_body(d);
+}
+
+template <typename R>
+__global__ void k_push_end_b(const SimDev<R> *__restrict__ ds,
+                                             const BatchDev *__restrict__ b)
+{
+    for (int i = threadIdx.x; i < b->nsim; i += blockDim.x) push_end_body(ds[i]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_fold(SimDev<R> d, int nplanes, R *o0, R *o1, R *o2)
+{
+    fold_body(d, xcd_remap(blockIdx.x, gridDim.x), nplanes, o0, o1, o2);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_fold_b(const SimDev<R> *__restrict__ ds,
+                                             const BatchDev *__restrict__ b)
+{
+    int2 it;
+    if (!batch_item(b, &it)) return;
+    const SimDev<R> &d = ds[it.x];
+    fold_body(d, it.y, 3, d.J[0], d.J[1], d.J[2]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_filter(SimDev<R> d, int nplanes, const R *i0,
+                                               const R *i1, const R *i2, R *o0, R *o1, R *o2)
+{
+    filter_body(d, xcd_remap(blockIdx.x, gridDim.x), nplanes, i0, i1, i2, o0, o1, o2);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_filter_b(const SimDev<R> *__restrict__ ds,
+                                             const BatchDev *__restrict__ b)
+{
+    int2 it;
+    if (!batch_item(b, &it)) return;
+    const SimDev<R> &d = ds[it.x];
+    if (d.npass == 0) return;
+    filter_body(d, it.y, 3, d.J[0], d.J[1], d.J[2], d.Jf[0], d.Jf[1], d.Jf[2]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_yee(SimDev<R> d)
+{
+    yee_body(d, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_yee_b(const SimDev<R> *__restrict__ ds,
+                                             const BatchDev *__restrict__ b)
+{
+    int2 it;
+    if (batch_item(b, &it)) yee_body(ds[it.x], it.y);
+}
+
+template <typename R>
+__global__ void k_step_end(SimDev<R> d)
+{
+    if (threadIdx.x == 0) step_end_body(d);
+}
+
+template <typename R>
+__global__ void k_step_end_b(const SimDev<R> *__restrict__ ds,
+                                             const BatchDev *__restrict__ b)
+{
+    for (int i = threadIdx.x; i < b->nsim; i += blockDim.x) step_end_body(ds[i]);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -1197,6 +1298,25 @@ hipError_t Launch<R>::copy_plane(const R *src, R *dst, long long n, hipStream_t 
     hipLaunchKernelGGL(k_copy<R>, dim3(NB_DIAG), dim3(NT), 0, s, src, dst, n);
     return hipGetLastError();
 }
+
+// One step of a batch: grid = the work-list capacity the graph was captured
+// for; `ds` and `b` live in device memory.
+template <typename R>
+hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_push_deposit_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    hipLaunchKernelGGL(k_push_end_b<R>, dim3(1), dim3(64), 0, s, ds, b);
+    hipLaunchKernelGGL(k_fold_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    hipLaunchKernelGGL(k_filter_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    hipLaunchKernelGGL(k_yee_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    hipLaunchKernelGGL(k_step_end_b<R>, dim3(1), dim3(64), 0, s, ds, b);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_step<float>(const SimDev<float> *, const BatchDev *, int,
+                                             hipStream_t);
+template hipError_t launch_batch_step<double>(const SimDev<double> *, const BatchDev *, int,
+                                              hipStream_t);
 
 template struct Launch<float>;
 template struct Launch<double>;

@@ -51,6 +51,20 @@ class Diag(C.Structure):
                 ("nshift", C.c_int), ("status", C.c_int)]
 
 
+class Request(C.Structure):
+    _fields_ = [("cfg", Cfg), ("nsteps", C.c_int), ("arrival_s", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("admit_s", C.c_double), ("done_s", C.c_double), ("diag", Diag),
+                ("status", C.c_int)]
+
+
+class ServeOpts(C.Structure):
+    _fields_ = [("batched", C.c_int), ("chunk_steps", C.c_int), ("max_batch", C.c_int),
+                ("diag_every", C.c_int)]
+
+
 class PicError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("libpic error %d: %s" % (code, msg))
@@ -108,6 +122,17 @@ def lib():
         L.pic_timing_read.argtypes = [_P, _DP, _LLP, _I, _P]
         L.pic_layout.restype = _I
         L.pic_layout.argtypes = [_P, _LLP, _I]
+        L.pic_batch_mem_bytes.restype = C.c_size_t
+        L.pic_batch_mem_bytes.argtypes = [_I, _LL]
+        L.pic_batch_create.restype = _I
+        L.pic_batch_create.argtypes = [_P, C.c_size_t, _I, _LL, C.POINTER(_P)]
+        L.pic_batch_step.restype = _I
+        L.pic_batch_step.argtypes = [_P, C.POINTER(_P), _I, _I, _P]
+        L.pic_batch_free.restype = _I
+        L.pic_batch_free.argtypes = [_P]
+        L.pic_serve.restype = _I
+        L.pic_serve.argtypes = [C.POINTER(Request), _I, _P, C.c_size_t, C.POINTER(ServeOpts),
+                                C.POINTER(Result), _DP, _LL, _LLP, _P]
         L.pic_strerror.restype = C.c_char_p
         L.pic_strerror.argtypes = [_I]
         L.pic_last_error.restype = C.c_char_p
@@ -297,3 +322,73 @@ class Simulation:
 
 def cfl_limit(dx, dy):
     return 1.0 / math.sqrt(1.0 / dx ** 2 + 1.0 / dy ** 2)
+
+
+def _diag_dict(d, ns):
+    return dict(e_energy=d.e_energy, b_energy=d.b_energy, ke=np.array(d.ke[:ns]),
+                total=d.total, charge=d.charge, gauss_res_max=d.gauss_res_max,
+                cont_res_max=d.cont_res_max, rho_max=d.rho_max, t=d.t,
+                n_particles=np.array(d.n_particles[:ns]), step=d.step, nshift=d.nshift,
+                status=d.status)
+
+
+class Batch:
+    """Device workspace that steps several Simulations with shared launches."""
+
+    def __init__(self, max_sims, max_tiles, device="cuda"):
+        import torch
+        L = lib()
+        n = L.pic_batch_mem_bytes(int(max_sims), int(max_tiles))
+        if n == 0:
+            raise PicError(PIC_E_ARG, "bad batch sizes")
+        self.arena = torch.empty(int(n), dtype=torch.uint8, device=device)
+        self._h = _P()
+        _check(L.pic_batch_create(_P(self.arena.data_ptr()), int(n), int(max_sims),
+                                  int(max_tiles), C.byref(self._h)))
+
+    def step(self, sims, nsteps=1, stream=None):
+        import torch
+        arr = (_P * len(sims))(*[s._h for s in sims])
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().pic_batch_step(self._h, arr, len(sims), int(nsteps), _P(st.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pic_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve(requests, budget_bytes, batched=True, chunk_steps=10, max_batch=0, device="cuda",
+          max_step_records=1 << 16):
+    """Serve `requests` = [(arrival_s, workload, nsteps), ...] through the
+    native continuous-batching loop within an HBM budget of budget_bytes.
+    Returns per-request times / diagnostics and the per-step batch times."""
+    import torch
+    n = len(requests)
+    reqs = (Request * n)()
+    for i, (arr, w, nsteps) in enumerate(requests):
+        reqs[i].cfg = make_cfg(w)
+        reqs[i].nsteps = int(nsteps)
+        reqs[i].arrival_s = float(arr)
+    out = (Result * n)()
+    opts = ServeOpts(int(bool(batched)), int(chunk_steps), int(max_batch), 0)
+    arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
+    step_ms = np.zeros(max_step_records)
+    nsteps_out = C.c_longlong(0)
+    st = torch.cuda.current_stream()
+    _check(lib().pic_serve(reqs, n, _P(arena.data_ptr()), arena.numel(), C.byref(opts), out,
+                           _dp(step_ms), len(step_ms), C.byref(nsteps_out), _P(st.cuda_stream)))
+    res = []
+    for i, (arr, w, nsteps) in enumerate(requests):
+        r = out[i]
+        res.append(dict(arrival_s=float(arr), admit_s=r.admit_s, done_s=r.done_s,
+                        latency_s=r.done_s - float(arr), status=r.status,
+                        diag=_diag_dict(r.diag, len(w.species))))
+    k = min(int(nsteps_out.value), len(step_ms))
+    return dict(results=res, step_ms=step_ms[:k].copy())

@@ -1,0 +1,116 @@
+"""Batched stepping and the serving loop on the GPU.
+
+The current of every simulation is summed in integers, so a simulation's
+state after N steps does not depend on which other simulations shared its
+launches: the tests require bitwise equal fields and equal particle sets,
+alone and in a batch whose membership changes between calls, and equal
+diagnostics between continuous batching and one-at-a-time serving.
+"""
+import numpy as np
+import pytest
+
+from inputs import SpeciesSpec, Workload, serving_requests
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2106_12485_amd import PIC_E_NOMEM, Batch, Simulation, mem_bytes, serve  # noqa: E402
+
+KEYS = ("uz", "uy", "ux", "y", "x", "iy", "ix")
+
+
+def same_particles(a, b):
+    oa = np.lexsort([a[c] for c in KEYS])
+    ob = np.lexsort([b[c] for c in KEYS])
+    return all(np.array_equal(a[c][oa], b[c][ob]) for c in KEYS)
+
+
+def small_workloads():
+    return [
+        Workload("thermal_48x40", 48, 40, 4.8, 4.0, 0.07, 30,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.15,) * 3)], seed=11),
+        Workload("twostream_64x64", 64, 64, 6.4, 6.4, 0.07, 30,
+                 [SpeciesSpec(-1.0, 0.5, ppc=(4, 4), uth=(0.05,) * 3, ufl=(0.4, 0, 0)),
+                  SpeciesSpec(-1.0, 0.5, ppc=(4, 4), uth=(0.05,) * 3, ufl=(-0.4, 0, 0))],
+                 filter_passes=1, filter_compensate=True, seed=12),
+        Workload("thermal_34x34", 34, 34, 3.4, 3.4, 0.07, 30,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(3, 1), uth=(0.3,) * 3)], filter_passes=2,
+                 seed=13),
+    ]
+
+
+def test_batch_alone_equals_mixed_with_changing_membership():
+    ws = small_workloads()
+    alone = []
+    for w in ws:
+        s = Simulation(w)
+        s.step(30)
+        alone.append(s)
+    mixed = [Simulation(w) for w in ws]
+    ntiles = sum(s.layout()["ntx"] * s.layout()["nty"] for s in mixed)
+    b = Batch(4, ntiles)
+    A, B, C = mixed
+    b.step([A], 5)
+    b.step([A, B], 10)
+    b.step([A, B, C], 15)
+    b.step([B, C], 5)
+    b.step([C], 10)
+    torch.cuda.synchronize()
+    for sa, sm, w in zip(alone, mixed, ws):
+        assert sm.energy()["step"] == sa.energy()["step"] == 30
+        assert np.array_equal(sa.get_fields(), sm.get_fields()), w.name
+        for k in range(len(w.species)):
+            assert same_particles(sa.get_particles(k), sm.get_particles(k)), (w.name, k)
+        assert sm.status() == 0
+
+
+def test_batch_restages_when_a_member_is_replaced():
+    # a freed handle's address may be reused by the next simulation; the batch
+    # must still step the new one
+    ws = small_workloads()
+    b = Batch(4, 64)
+    a = Simulation(ws[0])
+    b.step([a], 3)
+    a.close()
+    c = Simulation(ws[2])
+    b.step([c], 4)
+    torch.cuda.synchronize()
+    assert c.energy()["step"] == 4
+    ref = Simulation(ws[2])
+    ref.step(4)
+    assert np.array_equal(ref.get_fields(), c.get_fields())
+
+
+def test_serving_batched_equals_one_at_a_time_and_respects_budget():
+    reqs = []
+    for i, (t, w) in enumerate(serving_requests(n_requests=6, grids=(64, 128),
+                                                ppcs=((2, 2), (4, 4)), steps=40)):
+        reqs.append((0.002 * i, w, 40))
+    budget = sum(mem_bytes(w) for _, w, _ in reqs[:3]) + (64 << 20)
+    rb = serve(reqs, budget, batched=True, chunk_steps=7)
+    rf = serve(reqs, budget, batched=False, chunk_steps=7)
+    assert len(rb["step_ms"]) > 0 and len(rf["step_ms"]) > 0
+    for (t, w, n), a, b in zip(reqs, rb["results"], rf["results"]):
+        assert a["status"] == 0 and b["status"] == 0, (a["status"], b["status"])
+        da, db = a["diag"], b["diag"]
+        assert da["step"] == db["step"] == n
+        assert da["e_energy"] == db["e_energy"] and da["b_energy"] == db["b_energy"]
+        assert np.array_equal(da["n_particles"], db["n_particles"])
+        assert np.allclose(da["ke"], db["ke"], rtol=1e-12, atol=0)
+        assert a["done_s"] >= a["admit_s"] >= t - 1e-9
+        # the same request run alone through pic_step
+        s = Simulation(w)
+        s.step(n)
+        e = s.energy()
+        assert e["e_energy"] == da["e_energy"] and e["b_energy"] == da["b_energy"]
+    # a budget below one request: that request is refused, the others served
+    big = max(reqs, key=lambda r: mem_bytes(r[1]))
+    small = min(reqs, key=lambda r: mem_bytes(r[1]))
+    budget = mem_bytes(small[1]) + (16 << 20)
+    assert mem_bytes(big[1]) > budget
+    r = serve([(0.0, small[1], 5), (0.0, big[1], 5)], budget, batched=True, chunk_steps=5)
+    assert r["results"][0]["status"] == 0
+    assert r["results"][1]["status"] == PIC_E_NOMEM
