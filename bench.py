@@ -38,6 +38,30 @@ BYTES_PER_PARTICLE = {False: 2 * (4 + 5 * 4), True: 2 * (4 + 5 * 8)}
 BYTES_PER_CELL = {False: (6 + 3) * 4, True: (6 + 3) * 8}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_push_deposit_clouds_1024x1024_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_push_deposit launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (calibrated on a plain copy), or None if
+    that summary was taken on other kernel sources than the current ones."""
+    import hashlib
+    try:
+        vals = {}
+        for line in open(TRAFFIC_PROFILE):
+            parts = line.split()
+            if len(parts) == 2 and parts[0].endswith(("sha256", "per_launch")):
+                vals[parts[0]] = parts[1]
+        src = os.path.join(ROOT, "paper_2106_12485_amd", "csrc")
+        kh = hashlib.sha256(open(os.path.join(src, "pic_kernels.hip"), "rb").read()).hexdigest()
+        hh = hashlib.sha256(open(os.path.join(src, "pic_dev.h"), "rb").read()).hexdigest()
+        if vals.get("kernel_source_sha256") != kh or vals.get("header_source_sha256") != hh:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +75,12 @@ def parse():
                     help="warm-up and timed steps only (for rocprofv3)")
     ap.add_argument("--direct", action="store_true",
                     help="with --profile-only: launch kernels directly, not from the graph")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg and print its JSON")
+    ap.add_argument("--budget-gb", type=float, default=32.0,
+                    help="HBM budget of the serving loop")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -66,6 +96,57 @@ def copy_calibration(mib):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps(dict(copy_bytes=n * 4, launches=5)))
+
+
+def serving_leg(nreq, budget_gb, chunk=10):
+    """Stream of independent periodic plasmas (grids 64^2..512^2, 4/16/64 ppc,
+    thermal or two-stream, 200 steps each) served within an HBM budget:
+    capacity with every request present at t = 0, one at a time vs continuous
+    batching; then latency with Poisson arrivals at the one-at-a-time service
+    rate."""
+    from inputs import serving_requests
+    from paper_2106_12485_amd import serve
+    budget = int(budget_gb * 2 ** 30)
+    base = serving_requests(n_requests=nreq)
+    reqs0 = [(0.0, w, w.steps) for _, w in base]
+
+    def pushes(res):
+        return sum(float(r["diag"]["n_particles"].sum()) * n
+                   for r, (_, w, n) in zip(res["results"], reqs0))
+
+    def summary(res, reqs):
+        rs = res["results"]
+        ok = all(r["status"] == 0 for r in rs)
+        span = max(r["done_s"] for r in rs) - min(a for a, _, _ in reqs)
+        lat = np.array([r["latency_s"] for r in rs]) * 1e3
+        sm = res["step_ms"]
+        return dict(ok=ok, makespan_s=round(span, 4), requests_per_s=round(len(rs) / span, 3),
+                    pushes_per_s=pushes(res) / span,
+                    request_latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 3),
+                                            p99=round(float(np.percentile(lat, 99)), 3)),
+                    step_ms=dict(p50=round(float(np.percentile(sm, 50)), 4),
+                                 p99=round(float(np.percentile(sm, 99)), 4), n=int(len(sm))))
+    serve(reqs0[:4], budget, batched=True, chunk_steps=chunk)  # warm-up
+    fifo0 = summary(serve(reqs0, budget, batched=False, chunk_steps=chunk), reqs0)
+    bat0 = summary(serve(reqs0, budget, batched=True, chunk_steps=chunk), reqs0)
+    rate = fifo0["requests_per_s"]
+    rng = np.random.default_rng(0x5EED0003)
+    out = dict(workload="serving stream: %d periodic plasmas, grids 64..512^2, ppc 4/16/64, "
+                        "200 steps each, HBM budget %.0f GB" % (nreq, budget_gb),
+               chunk_steps=chunk,
+               all_at_t0=dict(one_at_a_time=fifo0, batched=bat0,
+                              speedup=round(fifo0["makespan_s"] / bat0["makespan_s"], 3)))
+    for load, key in ((1.0, "poisson_at_one_at_a_time_rate"),
+                      (2.0, "poisson_at_twice_one_at_a_time_rate")):
+        arr = np.cumsum(rng.exponential(1.0 / (load * rate), len(reqs0)))
+        arr -= arr[0]
+        reqsp = [(float(a), w, n) for a, (_, w, n) in zip(arr, reqs0)]
+        out[key] = dict(rate_per_s=round(load * rate, 3),
+                        one_at_a_time=summary(serve(reqsp, budget, batched=False,
+                                                    chunk_steps=chunk), reqsp),
+                        batched=summary(serve(reqsp, budget, batched=True, chunk_steps=chunk),
+                                        reqsp))
+    return out
 
 
 def cpu_baseline(w, nsteps):
@@ -104,6 +185,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.serve_only:
+        print(json.dumps(serving_leg(args.serve_requests, args.budget_gb)))
         return
     w = WORKLOADS[args.workload]()
     sim = Simulation(w, fp64=args.fp64)
@@ -159,15 +243,27 @@ def main():
                     w.species[0].ppc[1], dt=w.dt, filter_passes=w.filter_passes,
                     moving_window=w.moving_window),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                      frac=round(achieved / HBM_PEAK_GBS, 4),
+                      traffic=(None if args.workload != "clouds_1024x1024" or args.fp64
+                               else measured_traffic()),
                       kernel="k_push_deposit", avg_launch_ms=round(avg_push_s * 1e3, 4),
                       alg_bytes_per_launch=int(alg_bytes),
                       pushes_per_s_kernel=nparts / avg_push_s),
         kernel_ms_per_step={k: round(v[0] / max(v[1], 1), 4) for k, v in tk.items() if v[1]},
-        latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 4),
-                        p99=round(float(np.percentile(lat, 99)), 4)),
+        step_latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 4),
+                             p99=round(float(np.percentile(lat, 99)), 4)),
         particles_end=int(n_end), status=int(status),
     )
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        sv = serving_leg(args.serve_requests, args.budget_gb)
+        line["serving"] = sv
+        bp = sv["poisson_at_one_at_a_time_rate"]["batched"]
+        line["latency_ms"] = dict(p50=bp["step_ms"]["p50"], p99=bp["step_ms"]["p99"],
+                                  what="one batched step of the serving loop, Poisson "
+                                       "arrivals at the one-at-a-time service rate")
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line))
