@@ -32,7 +32,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+            ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
              "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -87,6 +87,7 @@ def _declare(L):
     for name in ("orc_push_deposit", "orc_filter", "orc_yee", "orc_field_advance"):
         getattr(L, name).argtypes = [_P]
     L.orc_step.argtypes = [_P, _I]
+    L.orc_set_threads.argtypes = [_P, _I]
     L.orc_charge.argtypes = [_P, _DP]
     L.orc_divergence.argtypes = [_P, _DP, _DP, _DP]
     L.orc_filter_plane.argtypes = [_P, _DP]
@@ -159,6 +160,11 @@ class OracleSim:
         if not self._h:
             raise ValueError("bad grid")
         self.nsp = 0
+
+    def set_threads(self, n: int):
+        """n > 1: run the particle loop as the paper's parallel for (private
+        current copies summed in thread order) and the grid loops over rows."""
+        self._L.orc_set_threads(self._h, int(n))
 
     def close(self):
         if self._h:

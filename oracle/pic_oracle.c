@@ -17,6 +17,15 @@
  * blocking, no fusion.  Only tests/, __graft_entry__.smoke() and bench.py's
  * cpu_baseline leg may load this file.  It shares no code with the HIP path.
  *
+ * By default everything runs on one thread.  orc_set_threads(s, n > 1)
+ * switches on the paper's own multicore strategy for the particle loop
+ * (Sec. 3.1, "parallel for"): the particles are cut into n contiguous
+ * chunks, each thread deposits into a private copy of the current, and the
+ * copies are summed in thread order.  Particles come out identical to the
+ * one-thread run; the current differs only by the order of the FP64 sums.
+ * The grid loops (filter, Yee, window shift) are split over rows, which
+ * changes no result.
+ *
  * Where the paper is silent the readings are (each is restated in the design doc):
  *   - normalised units: c = 1, time in 1/w_p, length in c/w_p, u = gamma v,
  *     fields in m c w_p / e, dE/dt = curl B - J, dB/dt = -curl E, div E = rho;
@@ -71,6 +80,9 @@ typedef struct {
     double *jf[3];    /* current actually used by the field solver */
     int nsp;
     orc_species sp[ORC_MAX_SPECIES];
+    int nthreads;     /* 1: sequential; n > 1: parallel particle loop */
+    double *priv;     /* private current copies of the parallel loop */
+    int priv_nt;
 } orc_sim;
 
 /* ------------------------------------------------------------------ */
@@ -165,6 +177,7 @@ orc_sim *orc_create(int nx, int ny, double lx, double ly, double dt, int window,
     s->npass = npass;
     s->compensate = compensate;
     s->seed = seed;
+    s->nthreads = 1;
     size_t nc = (size_t)nx * ny;
     for (int c = 0; c < 3; ++c) {
         s->e[c] = (double *)calloc(nc, sizeof(double));
@@ -191,6 +204,7 @@ void orc_destroy(orc_sim *s)
     for (int c = 0; c < 3; ++c) {
         free(s->e[c]); free(s->b[c]); free(s->jr[c]); free(s->jf[c]);
     }
+    free(s->priv);
     for (int k = 0; k < s->nsp; ++k) sp_free(&s->sp[k]);
     free(s);
 }
@@ -429,16 +443,16 @@ void orc_boris(double qm, double dt, const double E[3], const double B[3], doubl
 /* inside cell (i, j); (x0,y0)->(x1,y1) are cell-relative endpoints,   */
 /* f the fraction of the timestep spent on it, vz the z velocity.      */
 /* ------------------------------------------------------------------ */
-static void deposit_segment(orc_sim *s, double qp, int i, int j, double x0, double y0,
-                            double x1, double y1, double f, double vz)
+static void deposit_segment(const orc_sim *s, double *const *jt, double qp, int i, int j,
+                            double x0, double y0, double x1, double y1, double f, double vz)
 {
     double xm = 0.5 * (x0 + x1), ym = 0.5 * (y0 + y1);
     double cx = qp * (x1 - x0) * s->dx / s->dt;
     double cy = qp * (y1 - y0) * s->dy / s->dt;
-    fadd(s, s->jr[0], i, j, cx * (1 - ym));
-    fadd(s, s->jr[0], i, j + 1, cx * ym);
-    fadd(s, s->jr[1], i, j, cy * (1 - xm));
-    fadd(s, s->jr[1], i + 1, j, cy * xm);
+    fadd(s, jt[0], i, j, cx * (1 - ym));
+    fadd(s, jt[0], i, j + 1, cx * ym);
+    fadd(s, jt[1], i, j, cy * (1 - xm));
+    fadd(s, jt[1], i + 1, j, cy * xm);
     /* Jz: time average over the segment of the bilinear weight of each
      * node; along a straight line the weight is a quadratic in time and its
      * average is (S0x S0y + S1x S1y)/3 + (S0x S1y + S1x S0y)/6. */
@@ -448,15 +462,15 @@ static void deposit_segment(orc_sim *s, double qp, int i, int j, double x0, doub
         for (int a = 0; a < 2; ++a) {
             double w = (s0x[a] * s0y[b] + s1x[a] * s1y[b]) / 3.0 +
                        (s0x[a] * s1y[b] + s1x[a] * s0y[b]) / 6.0;
-            fadd(s, s->jr[2], i + a, j + b, qp * vz * f * w);
+            fadd(s, jt[2], i + a, j + b, qp * vz * f * w);
         }
 }
 
 /* Deposit the move of one particle starting at cell (ix, iy), offset (x, y),
  * displaced by (ddx, ddy) cells, cutting the path where it crosses a cell
  * boundary, in the order the path crosses them. */
-static void deposit_move(orc_sim *s, double qp, int ix, int iy, double x, double y,
-                         double ddx, double ddy, double vz)
+static void deposit_move(const orc_sim *s, double *const *jt, double qp, int ix, int iy,
+                         double x, double y, double ddx, double ddy, double vz)
 {
     double x1 = x + ddx, y1 = y + ddy;
     double tx = 2.0, ty = 2.0;
@@ -476,52 +490,114 @@ static void deposit_move(orc_sim *s, double qp, int ix, int iy, double x, double
         if (!(t1 > t0)) continue;
         double tm = 0.5 * (t0 + t1);
         int cx = (int)floor(x + tm * ddx), cy = (int)floor(y + tm * ddy);
-        deposit_segment(s, qp, ix + cx, iy + cy,
+        deposit_segment(s, jt, qp, ix + cx, iy + cy,
                         x + t0 * ddx - cx, y + t0 * ddy - cy,
                         x + t1 * ddx - cx, y + t1 * ddy - cy, t1 - t0, vz);
     }
 }
 
-/* Stages 1-3 for every particle: interpolate, push, move, deposit.  The
- * current of the step is accumulated in jr (zeroed first).  With the moving
- * window, particles whose new position is outside the box are removed. */
+/* Stages 1-3 for particles [q0, q1) of species p: interpolate, push, move,
+ * deposit into jt.  The kept particles are written compacted from index q0
+ * on; returns how many were kept.  With the moving window, particles whose
+ * new position is outside the box are removed. */
+static long long advance_range(const orc_sim *s, orc_species *p, double *const *jt,
+                               long long q0, long long q1)
+{
+    long long keep = q0;
+    for (long long q = q0; q < q1; ++q) {
+        double fl[6];
+        orc_gather(s, p->ix[q], p->iy[q], p->x[q], p->y[q], fl);
+        double u[3] = {p->ux[q], p->uy[q], p->uz[q]};
+        orc_boris(p->qm, s->dt, fl, fl + 3, u);
+        double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double ddx = s->dt * u[0] / (g * s->dx);
+        double ddy = s->dt * u[1] / (g * s->dy);
+        deposit_move(s, jt, p->qp, p->ix[q], p->iy[q], p->x[q], p->y[q], ddx, ddy, u[2] / g);
+        /* new cell and offset */
+        double xn = p->x[q] + ddx, yn = p->y[q] + ddy;
+        int di = (int)floor(xn), dj = (int)floor(yn);
+        xn -= di;
+        yn -= dj;
+        int ix = p->ix[q] + di, iy = p->iy[q] + dj;
+        if (xn >= 1.0) { xn -= 1.0; ix += 1; }
+        if (yn >= 1.0) { yn -= 1.0; iy += 1; }
+        iy = imod(iy, s->ny);
+        if (s->window) {
+            if (ix < 0 || ix >= s->nx) continue; /* left the box: removed */
+        } else {
+            ix = imod(ix, s->nx);
+        }
+        p->ix[keep] = ix; p->iy[keep] = iy; p->x[keep] = xn; p->y[keep] = yn;
+        p->ux[keep] = u[0]; p->uy[keep] = u[1]; p->uz[keep] = u[2];
+        ++keep;
+    }
+    return keep - q0;
+}
+
+static void move_particles(orc_species *p, long long to, long long from, long long n)
+{
+    if (to == from || n == 0) return;
+    memmove(p->ix + to, p->ix + from, n * sizeof(int));
+    memmove(p->iy + to, p->iy + from, n * sizeof(int));
+    memmove(p->x + to, p->x + from, n * sizeof(double));
+    memmove(p->y + to, p->y + from, n * sizeof(double));
+    memmove(p->ux + to, p->ux + from, n * sizeof(double));
+    memmove(p->uy + to, p->uy + from, n * sizeof(double));
+    memmove(p->uz + to, p->uz + from, n * sizeof(double));
+}
+
+/* Stages 1-3 for every particle.  The current of the step is accumulated in
+ * jr (zeroed first). */
 void orc_push_deposit(orc_sim *s)
 {
     size_t nc = (size_t)s->nx * s->ny;
     for (int c = 0; c < 3; ++c) memset(s->jr[c], 0, nc * sizeof(double));
+    const int nt = s->nthreads;
+    if (nt <= 1) {
+        for (int k = 0; k < s->nsp; ++k) {
+            orc_species *p = &s->sp[k];
+            p->n = advance_range(s, p, s->jr, 0, p->n);
+        }
+        return;
+    }
+    /* parallel for (Sec. 3.1): contiguous chunks, private current copies */
+    if (s->priv_nt != nt) {
+        free(s->priv);
+        s->priv = (double *)malloc((size_t)nt * 3 * nc * sizeof(double));
+        s->priv_nt = nt;
+    }
+    double *priv = s->priv;
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+    for (int t = 0; t < nt; ++t) memset(priv + (size_t)t * 3 * nc, 0, 3 * nc * sizeof(double));
+    long long *kept = (long long *)calloc((size_t)nt, sizeof(long long));
     for (int k = 0; k < s->nsp; ++k) {
         orc_species *p = &s->sp[k];
-        long long keep = 0;
-        for (long long q = 0; q < p->n; ++q) {
-            double fl[6];
-            orc_gather(s, p->ix[q], p->iy[q], p->x[q], p->y[q], fl);
-            double u[3] = {p->ux[q], p->uy[q], p->uz[q]};
-            orc_boris(p->qm, s->dt, fl, fl + 3, u);
-            double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            double ddx = s->dt * u[0] / (g * s->dx);
-            double ddy = s->dt * u[1] / (g * s->dy);
-            deposit_move(s, p->qp, p->ix[q], p->iy[q], p->x[q], p->y[q], ddx, ddy, u[2] / g);
-            /* new cell and offset */
-            double xn = p->x[q] + ddx, yn = p->y[q] + ddy;
-            int di = (int)floor(xn), dj = (int)floor(yn);
-            xn -= di;
-            yn -= dj;
-            int ix = p->ix[q] + di, iy = p->iy[q] + dj;
-            if (xn >= 1.0) { xn -= 1.0; ix += 1; }
-            if (yn >= 1.0) { yn -= 1.0; iy += 1; }
-            iy = imod(iy, s->ny);
-            if (s->window) {
-                if (ix < 0 || ix >= s->nx) continue; /* left the box: removed */
-            } else {
-                ix = imod(ix, s->nx);
-            }
-            p->ix[keep] = ix; p->iy[keep] = iy; p->x[keep] = xn; p->y[keep] = yn;
-            p->ux[keep] = u[0]; p->uy[keep] = u[1]; p->uz[keep] = u[2];
-            ++keep;
+        const long long n = p->n;
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+        for (int t = 0; t < nt; ++t) {
+            double *jt[3] = {priv + ((size_t)t * 3 + 0) * nc, priv + ((size_t)t * 3 + 1) * nc,
+                             priv + ((size_t)t * 3 + 2) * nc};
+            kept[t] = advance_range(s, p, jt, n * t / nt, n * (t + 1) / nt);
         }
-        p->n = keep;
+        long long to = 0;
+        for (int t = 0; t < nt; ++t) {
+            move_particles(p, to, n * t / nt, kept[t]);
+            to += kept[t];
+        }
+        p->n = to;
     }
+    /* reduction of the private copies, in thread order */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long long q = 0; q < (long long)nc; ++q)
+        for (int c = 0; c < 3; ++c) {
+            double v = 0.0;
+            for (int t = 0; t < nt; ++t) v += priv[((size_t)t * 3 + c) * nc + q];
+            s->jr[c][q] = v;
+        }
+    free(kept);
 }
+
+void orc_set_threads(orc_sim *s, int n) { s->nthreads = n < 1 ? 1 : n; }
 
 /* ------------------------------------------------------------------ */
 /* digital filter: 3-point stencil (w0, w1, w2) along one axis         */
@@ -531,6 +607,7 @@ static void stencil_x(const orc_sim *s, double *f, double w0, double w1, double 
     size_t nc = (size_t)s->nx * s->ny;
     double *t = (double *)malloc(nc * sizeof(double));
     memcpy(t, f, nc * sizeof(double));
+#pragma omp parallel for num_threads(s->nthreads) if (s->nthreads > 1)
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i)
             f[i + (size_t)j * s->nx] = w0 * fget(s, t, i - 1, j) + w1 * fget(s, t, i, j) +
@@ -543,6 +620,7 @@ static void stencil_y(const orc_sim *s, double *f, double w0, double w1, double 
     size_t nc = (size_t)s->nx * s->ny;
     double *t = (double *)malloc(nc * sizeof(double));
     memcpy(t, f, nc * sizeof(double));
+#pragma omp parallel for num_threads(s->nthreads) if (s->nthreads > 1)
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i)
             f[i + (size_t)j * s->nx] = w0 * fget(s, t, i, j - 1) + w1 * fget(s, t, i, j) +
@@ -576,6 +654,7 @@ void orc_filter(orc_sim *s)
 static void b_half(orc_sim *s)
 {
     double h = 0.5 * s->dt;
+#pragma omp parallel for num_threads(s->nthreads) if (s->nthreads > 1)
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i) {
             size_t q = i + (size_t)j * s->nx;
@@ -592,6 +671,7 @@ static void b_half(orc_sim *s)
 static void e_full(orc_sim *s)
 {
     double dt = s->dt;
+#pragma omp parallel for num_threads(s->nthreads) if (s->nthreads > 1)
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i) {
             size_t q = i + (size_t)j * s->nx;
@@ -619,6 +699,7 @@ static void window_shift(orc_sim *s)
 {
     for (int c = 0; c < 6; ++c) {
         double *f = c < 3 ? s->e[c] : s->b[c - 3];
+#pragma omp parallel for num_threads(s->nthreads) if (s->nthreads > 1)
         for (int j = 0; j < s->ny; ++j) {
             double *row = f + (size_t)j * s->nx;
             for (int i = 0; i + 1 < s->nx; ++i) row[i] = row[i + 1];

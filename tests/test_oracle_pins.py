@@ -498,3 +498,40 @@ def test_moving_window_injects_plasma_at_lab_density_edge():
     lab_first = max(0, 25 - sh)
     assert (cols[lab_first + 1:nx - 1] == ny * 2).all()
     assert cols[:max(lab_first - 1, 0)].sum() == 0
+
+
+# ---------------------------------------------------------------------------
+# the paper's multicore particle loop (Sec. 3.1) inside the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("window", [False, True])
+def test_parallel_for_mode_only_reorders_the_current_sums(window):
+    # private current copies summed in thread order change the FP64 sums'
+    # rounding only: after one step the particles are bitwise equal and J
+    # agrees to ~1e-15; later steps see fields that differ at that level
+    nx, ny = 48, 40
+    sims = []
+    for nt in (1, 4):
+        s = OracleSim(nx, ny, nx * 0.1, ny * 0.1, 0.07, window=window, filter_passes=1,
+                      filter_compensate=window, seed=9)
+        s.add_species(Species(-1.0, 1.0, x_lo=0.8 if window else -1e300, ppc=(2, 2),
+                              uth=(0.2, 0.2, 0.2), ufl=(0.3, 0.0, 0.1)))
+        if window:
+            s.add_laser(1.0, 10.0, 1.5, 0.5, 1.5, 2.0, ny * 0.05, 0.4)
+        s.set_threads(nt)
+        sims.append(s)
+    keys = ("ix", "iy", "x", "y", "ux", "uy", "uz")
+    for s in sims:
+        s.step(1)
+    p1, p4 = (s.get_particles(0) for s in sims)
+    assert all(np.array_equal(p1[k], p4[k]) for k in keys)
+    j1, j4 = (s.get_current(False) for s in sims)
+    assert np.abs(j1).max() > 0
+    assert np.abs(j1 - j4).max() <= 1e-13 * np.abs(j1).max()
+    for s in sims:
+        s.step(11)
+    assert sims[0].nshift == sims[1].nshift and (sims[0].nshift > 0) == window
+    p1, p4 = (s.get_particles(0) for s in sims)
+    assert all(np.array_equal(p1[k], p4[k]) for k in ("ix", "iy"))
+    assert max(np.abs(p1[k] - p4[k]).max() for k in keys[2:]) < 1e-10
+    f1, f4 = (s.get_fields() for s in sims)
+    assert np.abs(f1 - f4).max() <= 1e-10 * np.abs(f1).max()
