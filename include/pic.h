@@ -124,7 +124,10 @@ typedef struct {
  * (F = the current filter; zero up to round-off on periodic boxes).
  * cont_res_max = max over nodes of |(rho^n - rho^{n-1})/dt + div J^{n-1/2}|
  * with the unfiltered current of the last step; it is available only when the
- * previous pic_energy call was exactly one step earlier, else it is -1. */
+ * previous pic_energy call was exactly one step earlier, else it is -1.
+ * With the moving window both residuals are taken over window columns
+ * 3 <= i < nx - nshift - 3: particles leave at the left edge and the plasma
+ * loaded since t = 0 enters at the right. */
 typedef struct {
     double e_energy, b_energy;
     double ke[PIC_MAX_SPECIES];

@@ -26,6 +26,7 @@ constexpr int PX = TX + 3;          // LDS row pitch of a tile block
 constexpr int PY = TY + 3;
 constexpr int BP = PX * PY;         // cells of a tile block
 constexpr int NT = 256;             // threads per block (4 wavefronts)
+constexpr int NTP = 512;            // threads per push block (8 wavefronts)
 constexpr int MAX_SP = 4;
 constexpr int MAX_OUT = 2048;       // outbox slots per tile and species
 constexpr int MAX_FR = 4;           // largest filter halo (passes + compensator)
@@ -130,22 +131,24 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
 // Current and charge are summed in LDS as 64-bit fixed point: integer LDS
 // atomics run at the rate of plain LDS traffic on CDNA, floating-point ones
 // do not, and integer sums do not depend on the order of the additions, so
-// the result is bitwise reproducible.  A term v becomes trunc-toward-minus-
-// infinity of v * 2^e.  FP32 builds the two words from the float directly:
-// with y = v * 2^(e-32) (jq = 2^(e-32)), the high word is floor(y) and the low
-// word (y - floor(y)) * 2^32, both exact; FP64 converts v * 2^e (jq = 2^e).
-__device__ __forceinline__ void lds_acc(unsigned long long *p, float v, float jq)
+// the result is bitwise reproducible.  A term v enters as floor(v * 2^e).
+// Callers pass y = v * jq with the power-of-two scale jq folded into their
+// per-species prefactors, so y rounds exactly as v would.  FP32 (jq =
+// 2^(e-32)): the high word is floor(y) and the low word fract(y) * 2^32, both
+// exact; the hardware fract is clamped below 1, which moves a negative term
+// smaller than 2^-25 in y by less than 2^-24 in y.  FP64 (jq = 2^e): floor(y).
+__device__ __forceinline__ void lds_acc(unsigned long long *p, float y)
 {
-    const float y = v * jq;
-    const float hi = floorf(y);
-    const unsigned lo = (unsigned)((y - hi) * 4294967296.0f);
-    const unsigned long long q = ((unsigned long long)(unsigned)(int)hi << 32) | lo;
+    int hi;  // floor(y) converted in one instruction
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(hi) : "v"(y));
+    const unsigned lo = (unsigned)(__builtin_amdgcn_fractf(y) * 4294967296.0f);
+    const unsigned long long q = ((unsigned long long)(unsigned)hi << 32) | lo;
     __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void lds_acc(unsigned long long *p, double v, double jq)
+__device__ __forceinline__ void lds_acc(unsigned long long *p, double y)
 {
-    const long long q = (long long)floor(v * jq);
+    const long long q = (long long)floor(y);
     __hip_atomic_fetch_add(p, (unsigned long long)q, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }

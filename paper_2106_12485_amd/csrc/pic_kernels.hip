@@ -83,7 +83,8 @@ __device__ void maxwellian(const SpDev<R> &P, uint32_t key0, uint32_t key1, uint
 
 // ---------------------------------------------------------------------------
 // stage 3: Villasenor-Buneman deposit of one straight segment that lies in
-// the cell (lx+cx, ly+cy) of the tile block.  The segment is the part
+// the cell (lx+cx, ly+cy) of the tile block (prefactors qjx, qjy, qp include
+// the fixed-point scale).  The segment is the part
 // t in [ta, tb] of the step of a particle starting at offset (x, y) of cell
 // (lx, ly) with displacement (ddx, ddy) cells.  Its x extent is (tb-ta)*ddx,
 // taken from the displacement rather than from differences of positions so
@@ -94,7 +95,7 @@ __device__ void maxwellian(const SpDev<R> &P, uint32_t key0, uint32_t key1, uint
 template <typename R>
 __device__ __forceinline__ void deposit_segment(unsigned long long *sj, int lx, int ly, R x, R y,
                                                 R ddx, R ddy, R vz, R qjx, R qjy, R qp, R ta,
-                                                R tb, int cx, int cy, R jq)
+                                                R tb, int cx, int cy)
 {
     const R f = tb - ta;
     const R tm = R(0.5) * (ta + tb);
@@ -105,21 +106,21 @@ __device__ __forceinline__ void deposit_segment(unsigned long long *sj, int lx, 
     const R az = qp * vz * f, corr = sx * sy * R(1.0 / 12.0);
     const int k = (lx + cx + 1) + (ly + cy + 1) * PX;
     unsigned long long *jx = sj, *jy = sj + BP, *jz = sj + 2 * BP;
-    lds_acc(jx + k, ax * (R(1) - ym), jq);
-    lds_acc(jx + k + PX, ax * ym, jq);
-    lds_acc(jy + k, ay * (R(1) - xm), jq);
-    lds_acc(jy + k + 1, ay * xm, jq);
-    lds_acc(jz + k, az * ((R(1) - xm) * (R(1) - ym) + corr), jq);
-    lds_acc(jz + k + 1, az * (xm * (R(1) - ym) - corr), jq);
-    lds_acc(jz + k + PX, az * ((R(1) - xm) * ym - corr), jq);
-    lds_acc(jz + k + PX + 1, az * (xm * ym + corr), jq);
+    lds_acc(jx + k, ax * (R(1) - ym));
+    lds_acc(jx + k + PX, ax * ym);
+    lds_acc(jy + k, ay * (R(1) - xm));
+    lds_acc(jy + k + 1, ay * xm);
+    lds_acc(jz + k, az * ((R(1) - xm) * (R(1) - ym) + corr));
+    lds_acc(jz + k + 1, az * (xm * (R(1) - ym) - corr));
+    lds_acc(jz + k + PX, az * ((R(1) - xm) * ym - corr));
+    lds_acc(jz + k + PX + 1, az * (xm * ym + corr));
 }
 
 // Split the straight move at the cell boundaries it crosses (at most one per
 // axis since |ddx|, |ddy| < 1), in the order the path crosses them.
 template <typename R>
 __device__ __forceinline__ void deposit_move(unsigned long long *sj, int lx, int ly, R x, R y,
-                                             R ddx, R ddy, R vz, R qjx, R qjy, R qp, R jq)
+                                             R ddx, R ddy, R vz, R qjx, R qjy, R qp)
 {
     const R x1 = x + ddx, y1 = y + ddy;
     const int di = (x1 >= R(1)) - (x1 < R(0));
@@ -130,21 +131,21 @@ __device__ __forceinline__ void deposit_move(unsigned long long *sj, int lx, int
     const bool xfirst = tx <= ty;
     const R t1 = xfirst ? tx : ty, t2 = xfirst ? ty : tx;
     if (t1 > R(0))
-        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, R(0), t1, 0, 0, jq);
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, R(0), t1, 0, 0);
     if (t2 > t1)
         deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t1, t2, xfirst ? di : 0,
-                        xfirst ? 0 : dj, jq);
+                        xfirst ? 0 : dj);
     if (R(1) > t2)
-        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t2, R(1), di, dj, jq);
+        deposit_segment(sj, lx, ly, x, y, ddx, ddy, vz, qjx, qjy, qp, t2, R(1), di, dj);
 }
 
 // Load the six field planes of buffer `par` on the tile block (periodic wrap
 // in storage; gap columns hold zeros) and clear the current block.
-template <typename R>
+template <int BT, typename R>
 __device__ __forceinline__ void load_tile_fields(const SimDev<R> &d, int par, int x0, int y0,
                                                  int w, int h, R *sf, unsigned long long *sj)
 {
-    for (int k = threadIdx.x; k < BP; k += NT) {
+    for (int k = threadIdx.x; k < BP; k += BT) {
         const int lx = k % PX - 1, ly = k / PX - 1;
         const bool in = lx < w + 2 && ly < h + 2;
         const int gx = wrapi(x0 + lx, d.nxs), gy = wrapi(y0 + ly, d.ny);
@@ -191,7 +192,7 @@ __device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R
 // wavefront, and the ones that leave go to outbox opar ^ 1 with their
 // direction.  Particles leaving the moving window are dropped.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <int BT, typename R>
 __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
 {
     __shared__ R sf[6 * BP];
@@ -206,7 +207,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
     const int par = st->parity, origin = st->origin;
     const int pp = st->ppar, ob = st->opar;
     const bool pend = st->pend != 0;
-    load_tile_fields(d, par, x0, y0, w, h, sf, sj);
+    load_tile_fields<BT>(d, par, x0, y0, w, h, sf, sj);
 
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -228,7 +229,6 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
         const PartBuf<R> &bi = P.pb[pp];
         const PartBuf<R> &bo = P.pb[pp ^ 1];
         const unsigned n_own = (unsigned)bi.count[t];
-        const unsigned total = n_own + (unsigned)s_pre[N_DIR];
         const size_t base = (size_t)t * P.cap;
         // tile-uniform base pointers, indexed with 32-bit offsets
         const int *const ic = bi.cell + base;
@@ -243,37 +243,12 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
         R *const oux = bo.ux + base;
         R *const ouy = bo.uy + base;
         R *const ouz = bo.uz + base;
-        const R qjx = P.qp * d.jxs, qjy = P.qp * d.jys;
+        // deposit prefactors carry the fixed-point scale (a power of two)
+        const R qjx = P.qp * d.jxs * jq, qjy = P.qp * d.jys * jq, qps = P.qp * jq;
         const R tau = P.tau;
-        for (unsigned p0 = 0; p0 < total; p0 += NT) {
-            const unsigned p = p0 + threadIdx.x;
-            bool act = false;
-            int cell = 0;
-            R x = 0, y = 0, ux = 0, uy = 0, uz = 0;
-            if (p < n_own) {
-                const unsigned o4 = p * 4u, oR = p * (unsigned)sizeof(R);
-                cell = at(ic, o4);
-                x = at(ixp, oR);
-                y = at(iyp, oR);
-                ux = at(iux, oR);
-                uy = at(iuy, oR);
-                uz = at(iuz, oR);
-                act = true;
-            } else if (p < total) {
-                const int e = (int)(p - n_own);
-                int k = 0;
-                while (k < N_DIR - 1 && e >= s_pre[k + 1]) ++k;
-                const size_t o = (size_t)s_nb[k] * d.cap_out + (e - s_pre[k]);
-                if (P.ob_dir[ob][o] == s_want[k]) {
-                    cell = P.ob_cell[ob][o];
-                    x = P.ob_x[ob][o];
-                    y = P.ob_y[ob][o];
-                    ux = P.ob_ux[ob][o];
-                    uy = P.ob_uy[ob][o];
-                    uz = P.ob_uz[ob][o];
-                    act = true;
-                }
-            }
+        // Push, move and deposit one particle per lane (act: the lane holds
+        // one), then write the wavefront's stayers and leavers.
+        auto advance = [&](bool act, int cell, R x, R y, R ux, R uy, R uz) {
             bool stay = false, send = false;
             int ncell = 0, dir = 0;
             R xn = 0, yn = 0;
@@ -306,7 +281,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
                 // move and stage 3
                 const R ig2 = rsqrt1(R(1) + ux * ux + uy * uy + uz * uz);
                 const R ddx = d.dt_dx * ux * ig2, ddy = d.dt_dy * uy * ig2;
-                deposit_move(sj, lx, ly, x, y, ddx, ddy, uz * ig2, qjx, qjy, P.qp, jq);
+                deposit_move(sj, lx, ly, x, y, ddx, ddy, uz * ig2, qjx, qjy, qps);
                 xn = x + ddx;
                 yn = y + ddy;
                 int di = (xn >= R(1)) - (xn < R(0));
@@ -369,6 +344,58 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
                     }
                 }
             }
+        };
+        // Own particles, read one batch ahead: the loads of batch k+1 are in
+        // flight while batch k is pushed and deposited.
+        int nc = 0;
+        R nxv = 0, nyv = 0, nux = 0, nuy = 0, nuz = 0;
+        if (threadIdx.x < n_own) {
+            const unsigned o4 = threadIdx.x * 4u, oR = threadIdx.x * (unsigned)sizeof(R);
+            nc = at(ic, o4);
+            nxv = at(ixp, oR);
+            nyv = at(iyp, oR);
+            nux = at(iux, oR);
+            nuy = at(iuy, oR);
+            nuz = at(iuz, oR);
+        }
+        for (unsigned p0 = 0; p0 < n_own; p0 += BT) {
+            const unsigned p = p0 + threadIdx.x;
+            const int cell = nc;
+            const R x = nxv, y = nyv, ux = nux, uy = nuy, uz = nuz;
+            const unsigned pn = p + BT;
+            if (pn < n_own) {
+                const unsigned o4 = pn * 4u, oR = pn * (unsigned)sizeof(R);
+                nc = at(ic, o4);
+                nxv = at(ixp, oR);
+                nyv = at(iyp, oR);
+                nux = at(iux, oR);
+                nuy = at(iuy, oR);
+                nuz = at(iuz, oR);
+            }
+            advance(p < n_own, cell, x, y, ux, uy, uz);
+        }
+        // Leavers of the previous push from the 8 neighbours that moved here.
+        const unsigned n_in = (unsigned)s_pre[N_DIR];
+        for (unsigned e0 = 0; e0 < n_in; e0 += BT) {
+            const int e = (int)(e0 + threadIdx.x);
+            bool act = false;
+            int cell = 0;
+            R x = 0, y = 0, ux = 0, uy = 0, uz = 0;
+            if (e < (int)n_in) {
+                int k = 0;
+                while (k < N_DIR - 1 && e >= s_pre[k + 1]) ++k;
+                const size_t o = (size_t)s_nb[k] * d.cap_out + (e - s_pre[k]);
+                if (P.ob_dir[ob][o] == s_want[k]) {
+                    cell = P.ob_cell[ob][o];
+                    x = P.ob_x[ob][o];
+                    y = P.ob_y[ob][o];
+                    ux = P.ob_ux[ob][o];
+                    uy = P.ob_uy[ob][o];
+                    uz = P.ob_uz[ob][o];
+                    act = true;
+                }
+            }
+            advance(act, cell, x, y, ux, uy, uz);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -380,7 +407,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
     // one flush of the tile's current block per step
     R *out = d.blk + (size_t)t * 3 * BP;
     const double jqi = d.jq_inv;
-    for (int k = threadIdx.x; k < 3 * BP; k += NT) out[k] = (R)fx_value(sj[k], jqi);
+    for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = (R)fx_value(sj[k], jqi);
 }
 
 // After each push: both buffers flip and its outbox is pending.
@@ -885,15 +912,15 @@ __global__ __launch_bounds__(NT) void k_rho(SimDev<R> d)
         const PartBuf<R> &P = S.pb[d.st->ppar];
         const int n = P.count[t];
         const size_t base = (size_t)t * S.cap;
-        const R qp = S.qp;
+        const R qp = S.qp * d.jq;  // carries the fixed-point scale
         for (int p = threadIdx.x; p < n; p += NT) {
             const int c = P.cell[base + p];
             const R x = P.x[base + p], y = P.y[base + p];
             const int k = (cell_x(c) - x0 + 1) + (cell_y(c) - y0 + 1) * PX;
-            lds_acc(sr + k, qp * (R(1) - x) * (R(1) - y), d.jq);
-            lds_acc(sr + k + 1, qp * x * (R(1) - y), d.jq);
-            lds_acc(sr + k + PX, qp * (R(1) - x) * y, d.jq);
-            lds_acc(sr + k + PX + 1, qp * x * y, d.jq);
+            lds_acc(sr + k, qp * (R(1) - x) * (R(1) - y));
+            lds_acc(sr + k + 1, qp * x * (R(1) - y));
+            lds_acc(sr + k + PX, qp * (R(1) - x) * y);
+            lds_acc(sr + k + PX + 1, qp * x * y);
         }
     }
     __syncthreads();
@@ -964,6 +991,11 @@ __global__ __launch_bounds__(NT) void k_diag_grid(SimDev<R> d, int has_prev)
 {
     __shared__ double sred[NT];
     const int par = d.st->parity, origin = d.st->origin;
+    // With the moving window the residuals skip the columns next to the left
+    // edge (particles leave there and the fields beyond are held at zero) and
+    // the columns loaded since t = 0 (their neutralising background is not in
+    // the t = 0 baseline), each with a margin for the filter and the weights.
+    const int res_lo = 3, res_hi = d.nx - d.st->nshift - 3;
     const R *F[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) F[c] = par ? d.F[1][c] : d.F[0][c];
@@ -973,14 +1005,16 @@ __global__ __launch_bounds__(NT) void k_diag_grid(SimDev<R> d, int has_prev)
     for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < ncell;
          g += (long long)gridDim.x * NT) {
         const int gx = (int)(g % d.nxs), gy = (int)(g / d.nxs);
-        if (d.window && window_col(gx, origin, d.nxs) >= d.nx) continue;
+        const int wc = d.window ? window_col(gx, origin, d.nxs) : 0;
+        if (d.window && wc >= d.nx) continue;
         const double ex = F[0][g], ey = F[1][g], ez = F[2][g];
         const double bx = F[3][g], by = F[4][g], bz = F[5][g];
         e2 += ex * ex + ey * ey + ez * ez;
         b2 += bx * bx + by * by + bz * bz;
+        rm = fmax(rm, fabs((double)d.rho[g]));
+        if (d.window && (wc < res_lo || wc >= res_hi)) continue;
         const double gres = div_at(F[0], F[1], d, gx, gy, origin) - (double)d.rho_f[g] - d.g0[g];
         gm = fmax(gm, fabs(gres));
-        rm = fmax(rm, fabs((double)d.rho[g]));
         if (has_prev) {
             const double cres = ((double)d.rho[g] - (double)d.rho_prev[g]) * idt +
                                 div_at(d.J[0], d.J[1], d, gx, gy, origin);
@@ -1013,7 +1047,7 @@ __global__ __launch_bounds__(NT) void k_diag_ke(SimDev<R> d)
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    load_tile_fields(d, d.st->parity, x0, y0, w, h, sf, (unsigned long long *)nullptr);
+    load_tile_fields<NT>(d, d.st->parity, x0, y0, w, h, sf, (unsigned long long *)nullptr);
     __syncthreads();
     for (int s = 0; s < d.nsp; ++s) {
         const SpDev<R> &S = d.sp[s];
@@ -1105,10 +1139,18 @@ __device__ __forceinline__ bool batch_item(const BatchDev *__restrict__ b, int2 
     return true;
 }
 
+// Waves per SIMD the single-simulation push is compiled for: FP32 fits four
+// 512-thread blocks per CU in 64 VGPRs; FP64 needs more registers.  Blocks of
+// 512 threads halve the time one tile occupies its CU, which shortens the
+// drain at the end of the launch, when too few tiles are left to fill the GPU.
+template <typename R> struct PushWaves { static constexpr int n = 8; };
+template <> struct PushWaves<double> { static constexpr int n = 4; };
+
 template <typename R>
-__global__ __launch_bounds__(NT, 8) void k_push_deposit(SimDev<R> d)
+__global__ __launch_bounds__(NTP) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
+k_push_deposit(SimDev<R> d)
 {
-    push_body(d, xcd_remap(blockIdx.x, gridDim.x));
+    push_body<NTP>(d, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename R>
@@ -1116,7 +1158,7 @@ __global__ __launch_bounds__(NT) void k_push_deposit_b(const SimDev<R> *__restri
                                              const BatchDev *__restrict__ b)
 {
     int2 it;
-    if (batch_item(b, &it)) push_body(ds[it.x], it.y);
+    if (batch_item(b, &it)) push_body<NT>(ds[it.x], it.y);
 }
 
 template <typename R>
@@ -1199,7 +1241,7 @@ __global__ void k_step_end_b(const SimDev<R> *__restrict__ ds,
 template <typename R>
 hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NTP), 0, s, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_push_end<R>, dim3(1), dim3(64), 0, s, d);
