@@ -283,18 +283,21 @@ typedef struct {
 typedef struct {
     int batched;         /* 1: continuous batching; 0: one at a time, in order */
     int chunk_steps;     /* steps between admission points (>= 1) */
-    int max_batch;       /* most simulations stepped together (<= 0: 256) */
+    int max_batch;       /* most simulations running at once (<= 0: 256) */
     int diag_every;      /* unused if 0; else pic_energy each that many steps */
 } pic_serve_opts;
 
 /* Serve n requests in real time: a request is queued at its arrival time,
  * admitted (first fit, in arrival order) when its pic_mem_bytes fits in the
- * free part of `arena` (the HBM budget), initialised on a second stream while
- * the batch keeps running, stepped with the batch in chunks of at most
- * chunk_steps, and retired when done, freeing its memory.  out[i] receives
- * request i's times and final diagnostics.  step_ms (capacity cap_steps,
- * may be NULL) receives the time per batched step of every chunk and
- * *n_steps their number.  Returns PIC_OK or the first host-side error. */
+ * free part of `arena` (the HBM budget), initialised on a stream of its own
+ * while the running set keeps stepping, stepped with the running set in
+ * lockstep chunks of at most chunk_steps (shared launches, pic_batch_step; a
+ * set of one runs its own step graph), and retired when done, freeing its
+ * memory.  One at a time (batched = 0) runs the requests alone, in arrival
+ * order.  out[i] receives request i's times and final diagnostics.  step_ms
+ * (capacity cap_steps, may be NULL) receives the time per step of every chunk
+ * and *n_steps their number.  The call returns when all its device work is
+ * done.  Returns PIC_OK or the first host-side error. */
 int pic_serve(const pic_request *reqs, int n, void *arena, size_t arena_bytes,
               const pic_serve_opts *opts, pic_result *out, double *step_ms,
               long long cap_steps, long long *n_steps, void *stream);

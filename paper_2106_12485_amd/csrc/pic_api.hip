@@ -1119,7 +1119,7 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
     if (n < 0 || (n > 0 && (!reqs || !out)) || !arena || !opts || ((uintptr_t)arena & 255))
         return fail(PIC_E_ARG, "bad serving arguments");
     const int chunk = std::max(1, opts->chunk_steps);
-    const int max_batch = opts->batched ? (opts->max_batch > 0 ? opts->max_batch : 256) : 1;
+    const int max_active = opts->batched ? (opts->max_batch > 0 ? opts->max_batch : 256) : 1;
     if (n_steps) *n_steps = 0;
     for (int i = 0; i < n; ++i) {
         std::memset(&out[i], 0, sizeof(out[i]));
@@ -1132,22 +1132,31 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
         if (layout(&reqs[i].cfg, &L) == PIC_OK) max_tiles += L.ntiles;
     }
     max_tiles = std::max(1LL, std::min(max_tiles, 1LL << 22));
-    const size_t bws = pic_batch_mem_bytes(max_batch, max_tiles);
-    if (arena_bytes < bws) return fail(PIC_E_NOMEM, "budget smaller than the batch workspace");
+    const size_t bws = align256(pic_batch_mem_bytes(max_active, max_tiles));
+    if (arena_bytes < bws + 256) return fail(PIC_E_NOMEM, "budget smaller than the batch workspace");
     pic_batch *batch = nullptr;
-    int rc = pic_batch_create(arena, bws, max_batch, max_tiles, &batch);
+    int rc = pic_batch_create(arena, bws, max_active, max_tiles, &batch);
     if (rc) return rc;
-    char *pool = (char *)arena + bws;
-    ArenaAlloc alloc(arena_bytes - bws);
     hipStream_t sa = (hipStream_t)stream, sb = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
-    if (he != hipSuccess) {
+    auto teardown = [&] {
+        (void)hipStreamSynchronize(sa);
+        if (sb) (void)hipStreamSynchronize(sb);
         pic_batch_free(batch);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (sb) (void)hipStreamDestroy(sb);
+    };
+    if (he != hipSuccess) {
+        teardown();
         return fail(PIC_E_HIP, std::string("serving set-up: ") + hipGetErrorString(he));
     }
+    char *pool = (char *)arena + bws;
+    const size_t pool_bytes = (arena_bytes - bws) & ~(size_t)255;
+    ArenaAlloc alloc(pool_bytes);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -1161,36 +1170,23 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
     std::vector<pic_sim *> sims;
     int next = 0, done = 0;
     long long ns = 0;
-    rc = PIC_OK;
-    while (done < n && rc == PIC_OK) {
+    // admit queued requests, first fit in arrival order (one at a time: strictly
+    // in order), initialising them on stream sb while the step stream runs
+    auto admit = [&] {
         const double tnow = now();
         while (next < n && reqs[order[next]].arrival_s <= tnow) queue.push_back(order[next++]);
-        // launch a chunk for the running set
-        int k = 0;
-        if (!active.empty()) {
-            k = chunk;
-            for (const Active &a : active) k = std::min(k, a.left);
-            sims.clear();
-            for (const Active &a : active) sims.push_back(a.sim);
-            (void)hipEventRecord(e0, sa);
-            rc = opts->batched ? pic_batch_step(batch, sims.data(), (int)sims.size(), k, sa)
-                               : pic_step(active[0].sim, k, sa);
-            (void)hipEventRecord(e1, sa);
-            if (rc) break;
-        }
-        // admit while the chunk runs: first fit in arrival order
-        for (size_t qi = 0; qi < queue.size() && (int)active.size() < max_batch;) {
-            if (!opts->batched && !active.empty()) break;
+        for (size_t qi = 0; qi < queue.size() && (int)active.size() < max_active;) {
             const int r = queue[qi];
             const size_t need = pic_mem_bytes(&reqs[r].cfg);
-            if (need == 0) {
-                out[r].status = PIC_E_ARG;
+            if (need == 0 || align256(need) > pool_bytes) {
+                out[r].status = need == 0 ? PIC_E_ARG : PIC_E_NOMEM;
                 ++done;
                 queue.erase(queue.begin() + qi);
                 continue;
             }
             const long long off = alloc.take(need);
             if (off < 0) {
+                if (!opts->batched) break;
                 ++qi;
                 continue;
             }
@@ -1204,20 +1200,10 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
                 continue;
             }
             out[r].admit_s = now();
-            active.push_back(Active{r, sim, (size_t)off, need, reqs[r].nsteps});
-            if (reqs[r].nsteps <= 0) active.back().left = 0;
+            active.push_back(Active{r, sim, (size_t)off, need, std::max(0, reqs[r].nsteps)});
         }
-        if (k > 0) {
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (step_ms && ns < cap_steps) step_ms[ns] = ms / k;
-            ++ns;
-            for (Active &a : active)
-                if (a.sim != nullptr && std::find(sims.begin(), sims.end(), a.sim) != sims.end())
-                    a.left -= k;
-        }
-        // retire the finished ones
+    };
+    auto retire = [&] {
         for (size_t ai = 0; ai < active.size();) {
             Active &a = active[ai];
             if (a.left > 0) {
@@ -1231,22 +1217,41 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
             ++done;
             active.erase(active.begin() + ai);
         }
-        if (active.empty() && queue.empty() && next < n) {
-            const double wait = reqs[order[next]].arrival_s - now();
-            if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
-        } else if (active.empty() && !queue.empty() && k == 0) {
-            // nothing fits although nothing runs: the request exceeds the budget
-            const int r = queue.front();
-            out[r].status = PIC_E_NOMEM;
-            queue.erase(queue.begin());
-            ++done;
+    };
+    while (done < n && rc == PIC_OK) {
+        admit();
+        retire();
+        if (active.empty()) {
+            if (queue.empty() && next < n) {
+                const double wait = reqs[order[next]].arrival_s - now();
+                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+            }
+            continue;
         }
+        // one chunk of the running set, all members in lockstep
+        int k = chunk;
+        sims.clear();
+        for (const Active &a : active) {
+            sims.push_back(a.sim);
+            k = std::min(k, a.left);
+        }
+        (void)hipEventRecord(e0, sa);
+        // a batch of one runs the simulation's own step graph
+        rc = sims.size() > 1 ? pic_batch_step(batch, sims.data(), (int)sims.size(), k, sa)
+                             : pic_step(sims[0], k, sa);
+        (void)hipEventRecord(e1, sa);
+        if (rc) break;
+        admit();  // while the chunk runs
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (step_ms && ns < cap_steps) step_ms[ns] = ms / k;
+        ++ns;
+        for (Active &a : active)
+            if (std::find(sims.begin(), sims.end(), a.sim) != sims.end()) a.left -= k;
     }
     for (Active &a : active) pic_free(a.sim);
     if (n_steps) *n_steps = ns;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipStreamDestroy(sb);
-    pic_batch_free(batch);
+    teardown();
     return rc;
 }

@@ -27,6 +27,7 @@ constexpr int PY = TY + 3;
 constexpr int BP = PX * PY;         // cells of a tile block
 constexpr int NT = 256;             // threads per block (4 wavefronts)
 constexpr int NTP = 512;            // threads per push block (8 wavefronts)
+constexpr int NTB = 512;            // threads per batched push block
 constexpr int MAX_SP = 4;
 constexpr int MAX_OUT = 2048;       // outbox slots per tile and species
 constexpr int MAX_FR = 4;           // largest filter halo (passes + compensator)
@@ -153,18 +154,32 @@ __device__ __forceinline__ void lds_acc(unsigned long long *p, double y)
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Pointers in the descriptors are generic; every array they reach is in
+// device memory.  Pointers loaded from a descriptor table in memory (the
+// batched kernels) cannot be proven global by the compiler, which then emits
+// flat accesses with 64-bit vector addresses; glob() states the address space.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T *p)
+{
+    return (gptr<T>)p;
+}
+
 // element at a 32-bit byte offset from a wave-uniform base pointer (keeps the
 // address computation in 32 bits: base in SGPRs, offset in one VGPR)
 template <typename T>
-__device__ __forceinline__ T &at(T *base, unsigned byte_off)
+__device__ __forceinline__ __attribute__((address_space(1))) T &at(T *base, unsigned byte_off)
 {
-    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+    return *(gptr<T>)(reinterpret_cast<char *>(base) + byte_off);
 }
 
 template <typename T>
-__device__ __forceinline__ const T &at(const T *base, unsigned byte_off)
+__device__ __forceinline__ const __attribute__((address_space(1))) T &at(const T *base,
+                                                                         unsigned byte_off)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    return *(gptr<const T>)(reinterpret_cast<const char *>(base) + byte_off);
 }
 
 __device__ __forceinline__ double fx_value(unsigned long long q, double jq_inv)

@@ -152,7 +152,7 @@ __device__ __forceinline__ void load_tile_fields(const SimDev<R> &d, int par, in
         const size_t g = in ? (size_t)gx + (size_t)gy * d.nxs : 0;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            const R *Fc = par ? d.F[1][c] : d.F[0][c];
+            const gptr<const R> Fc = glob<const R>(par ? d.F[1][c] : d.F[0][c]);
             sf[c * BP + k] = in ? Fc[g] : R(0);
         }
         if (sj) {
@@ -180,7 +180,7 @@ __device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R
         s_nb[threadIdx.x] = nb;
         // particles that moved from nb into t stepped by (-ox, -oy)
         s_want[threadIdx.x] = (unsigned char)dir_index(-ox, -oy);
-        s_len[threadIdx.x] = pend ? P.ob_count[ob][nb] : 0;
+        s_len[threadIdx.x] = pend ? glob(P.ob_count[ob])[nb] : 0;
     }
 }
 
@@ -203,7 +203,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    const DevState *st = d.st;
+    const gptr<const DevState> st = glob<const DevState>(d.st);
     const int par = st->parity, origin = st->origin;
     const int pp = st->ppar, ob = st->opar;
     const bool pend = st->pend != 0;
@@ -228,7 +228,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
         __syncthreads();
         const PartBuf<R> &bi = P.pb[pp];
         const PartBuf<R> &bo = P.pb[pp ^ 1];
-        const unsigned n_own = (unsigned)bi.count[t];
+        const unsigned n_own = (unsigned)glob(bi.count)[t];
         const size_t base = (size_t)t * P.cap;
         // tile-uniform base pointers, indexed with 32-bit offsets
         const int *const ic = bi.cell + base;
@@ -318,7 +318,8 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
                         at(ouy, oR) = uy;
                         at(ouz, oR) = uz;
                     } else {
-                        atomicOr(&d.st->err, ERR_CAPACITY);
+                        __hip_atomic_fetch_or(&glob(d.st)->err, ERR_CAPACITY, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
@@ -332,15 +333,16 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
                     const int slot = off + (int)__popcll(ml & below);
                     if (slot < d.cap_out) {
                         const size_t o = obase + slot;
-                        P.ob_cell[ob ^ 1][o] = ncell;
-                        P.ob_dir[ob ^ 1][o] = (unsigned char)dir;
-                        P.ob_x[ob ^ 1][o] = xn;
-                        P.ob_y[ob ^ 1][o] = yn;
-                        P.ob_ux[ob ^ 1][o] = ux;
-                        P.ob_uy[ob ^ 1][o] = uy;
-                        P.ob_uz[ob ^ 1][o] = uz;
+                        glob(P.ob_cell[ob ^ 1])[o] = ncell;
+                        glob(P.ob_dir[ob ^ 1])[o] = (unsigned char)dir;
+                        glob(P.ob_x[ob ^ 1])[o] = xn;
+                        glob(P.ob_y[ob ^ 1])[o] = yn;
+                        glob(P.ob_ux[ob ^ 1])[o] = ux;
+                        glob(P.ob_uy[ob ^ 1])[o] = uy;
+                        glob(P.ob_uz[ob ^ 1])[o] = uz;
                     } else {
-                        atomicOr(&d.st->err, ERR_CAPACITY);
+                        __hip_atomic_fetch_or(&glob(d.st)->err, ERR_CAPACITY, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
@@ -385,13 +387,13 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
                 int k = 0;
                 while (k < N_DIR - 1 && e >= s_pre[k + 1]) ++k;
                 const size_t o = (size_t)s_nb[k] * d.cap_out + (e - s_pre[k]);
-                if (P.ob_dir[ob][o] == s_want[k]) {
-                    cell = P.ob_cell[ob][o];
-                    x = P.ob_x[ob][o];
-                    y = P.ob_y[ob][o];
-                    ux = P.ob_ux[ob][o];
-                    uy = P.ob_uy[ob][o];
-                    uz = P.ob_uz[ob][o];
+                if (glob(P.ob_dir[ob])[o] == s_want[k]) {
+                    cell = glob(P.ob_cell[ob])[o];
+                    x = glob(P.ob_x[ob])[o];
+                    y = glob(P.ob_y[ob])[o];
+                    ux = glob(P.ob_ux[ob])[o];
+                    uy = glob(P.ob_uy[ob])[o];
+                    uz = glob(P.ob_uz[ob])[o];
                     act = true;
                 }
             }
@@ -399,13 +401,13 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            bo.count[t] = min(s_out, P.cap);
-            P.ob_count[ob ^ 1][t] = min(s_nob, d.cap_out);
+            glob(bo.count)[t] = min(s_out, P.cap);
+            glob(P.ob_count[ob ^ 1])[t] = min(s_nob, d.cap_out);
         }
         __syncthreads();
     }
     // one flush of the tile's current block per step
-    R *out = d.blk + (size_t)t * 3 * BP;
+    const gptr<R> out = glob(d.blk + (size_t)t * 3 * BP);
     const double jqi = d.jq_inv;
     for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = (R)fx_value(sj[k], jqi);
 }
@@ -498,7 +500,7 @@ __device__ __forceinline__ void fold_body(const SimDev<R> &d, const int t, int n
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    const int origin = d.st->origin;
+    const int origin = glob(d.st)->origin;
     for (int k = threadIdx.x; k < w * h; k += NT) {
         const int lx = k % w, ly = k / w;
         const int gx = x0 + lx, gy = y0 + ly;
@@ -513,8 +515,8 @@ __device__ __forceinline__ void fold_body(const SimDev<R> &d, const int t, int n
                 const int wn = min(TX, d.nxs - txn * TX);
                 const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
                 if (px < -1 || px >= wn + 2) continue;
-                const R *b = d.blk + (size_t)(txn + tyn * d.ntx) * 3 * BP + (px + 1) +
-                             (py + 1) * PX;
+                const gptr<const R> b = glob<const R>(
+                    d.blk + (size_t)(txn + tyn * d.ntx) * 3 * BP + (px + 1) + (py + 1) * PX);
                 a0 += b[0];
                 if (nplanes > 1) {
                     a1 += b[BP];
@@ -524,10 +526,10 @@ __device__ __forceinline__ void fold_body(const SimDev<R> &d, const int t, int n
         }
         const bool gap = d.window && window_col(gx, origin, d.nxs) >= d.nx;
         const size_t g = (size_t)gx + (size_t)gy * d.nxs;
-        o0[g] = gap ? R(0) : a0;
+        glob(o0)[g] = gap ? R(0) : a0;
         if (nplanes > 1) {
-            o1[g] = gap ? R(0) : a1;
-            o2[g] = gap ? R(0) : a2;
+            glob(o1)[g] = gap ? R(0) : a1;
+            glob(o2)[g] = gap ? R(0) : a2;
         }
     }
 }
@@ -548,7 +550,7 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    const int origin = d.st->origin;
+    const int origin = glob(d.st)->origin;
     const int rf = d.npass + (d.compensate ? 1 : 0);
     const R N = (R)d.npass;
     for (int k = threadIdx.x; k < QX; k += NT) {
@@ -557,8 +559,8 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
         s_gap[k] = d.window && window_col(gx, origin, d.nxs) >= d.nx;
     }
     for (int pl = 0; pl < nplanes; ++pl) {
-        const R *in = pl == 0 ? i0 : (pl == 1 ? i1 : i2);
-        R *out = pl == 0 ? o0 : (pl == 1 ? o1 : o2);
+        const gptr<const R> in = glob(pl == 0 ? i0 : (pl == 1 ? i1 : i2));
+        const gptr<R> out = glob(pl == 0 ? o0 : (pl == 1 ? o1 : o2));
         __syncthreads();
         for (int k = threadIdx.x; k < QX * QY; k += NT) {
             const int lx = k % QX - MAX_FR, ly = k / QX - MAX_FR;
@@ -627,7 +629,7 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    const int par = d.st->parity, origin = d.st->origin;
+    const int par = glob(d.st)->parity, origin = glob(d.st)->origin;
     for (int k = threadIdx.x; k < PX; k += NT)
         s_gap[k] = d.window && window_col(wrapi(x0 + k - 1, d.nxs), origin, d.nxs) >= d.nx;
     for (int k = threadIdx.x; k < BP; k += NT) {
@@ -637,11 +639,11 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
             in ? (size_t)wrapi(x0 + lx, d.nxs) + (size_t)wrapi(y0 + ly, d.ny) * d.nxs : 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const R *Fe = par ? d.F[1][c] : d.F[0][c];
-            const R *Fb = par ? d.F[1][3 + c] : d.F[0][3 + c];
+            const gptr<const R> Fe = glob<const R>(par ? d.F[1][c] : d.F[0][c]);
+            const gptr<const R> Fb = glob<const R>(par ? d.F[1][3 + c] : d.F[0][3 + c]);
             e[c * BP + k] = in ? Fe[g] : R(0);
             b[c * BP + k] = in ? Fb[g] : R(0);
-            jl[c * BP + k] = in ? d.Jf[c][g] : R(0);
+            jl[c * BP + k] = in ? glob<const R>(d.Jf[c])[g] : R(0);
         }
     }
     __syncthreads();
@@ -690,12 +692,12 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
             const R nby = gp ? R(0) : b[BP + k] + hdt * dEz_dx;
             const R nbz = gp ? R(0) : b[2 * BP + k] - hdt * (dEy_dx - dEx_dy);
             const size_t g = (size_t)(x0 + i) + (size_t)(y0 + j) * d.nxs;
-            (npar ? d.F[1][0] : d.F[0][0])[g] = e[k];
-            (npar ? d.F[1][1] : d.F[0][1])[g] = e[BP + k];
-            (npar ? d.F[1][2] : d.F[0][2])[g] = e[2 * BP + k];
-            (npar ? d.F[1][3] : d.F[0][3])[g] = nbx;
-            (npar ? d.F[1][4] : d.F[0][4])[g] = nby;
-            (npar ? d.F[1][5] : d.F[0][5])[g] = nbz;
+            glob(npar ? d.F[1][0] : d.F[0][0])[g] = e[k];
+            glob(npar ? d.F[1][1] : d.F[0][1])[g] = e[BP + k];
+            glob(npar ? d.F[1][2] : d.F[0][2])[g] = e[2 * BP + k];
+            glob(npar ? d.F[1][3] : d.F[0][3])[g] = nbx;
+            glob(npar ? d.F[1][4] : d.F[0][4])[g] = nby;
+            glob(npar ? d.F[1][5] : d.F[0][5])[g] = nbz;
         }
     }
 }
@@ -1139,6 +1141,8 @@ __device__ __forceinline__ bool batch_item(const BatchDev *__restrict__ b, int2 
     return true;
 }
 
+
+
 // Waves per SIMD the single-simulation push is compiled for: FP32 fits four
 // 512-thread blocks per CU in 64 VGPRs; FP64 needs more registers.  Blocks of
 // 512 threads halve the time one tile occupies its CU, which shortens the
@@ -1154,11 +1158,12 @@ k_push_deposit(SimDev<R> d)
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT) void k_push_deposit_b(const SimDev<R> *__restrict__ ds,
+__global__ __launch_bounds__(NTB) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
+k_push_deposit_b(const SimDev<R> *__restrict__ ds,
                                              const BatchDev *__restrict__ b)
 {
     int2 it;
-    if (batch_item(b, &it)) push_body<NT>(ds[it.x], it.y);
+    if (batch_item(b, &it)) push_body<NTB>(ds[it.x], it.y);
 }
 
 template <typename R>
@@ -1346,7 +1351,7 @@ hipError_t Launch<R>::copy_plane(const R *src, R *dst, long long n, hipStream_t 
 template <typename R>
 hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_push_deposit_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    hipLaunchKernelGGL(k_push_deposit_b<R>, dim3(grid), dim3(NTB), 0, s, ds, b);
     hipLaunchKernelGGL(k_push_end_b<R>, dim3(1), dim3(64), 0, s, ds, b);
     hipLaunchKernelGGL(k_fold_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
     hipLaunchKernelGGL(k_filter_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
