@@ -224,8 +224,10 @@ int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream);
  * of pic_deposit / pic_field_advance / pic_step (which then launch directly,
  * not from the graph).  pic_timing(sim, 1) resets and starts, 0 stops.
  * pic_timing_read fills ms[k] (summed milliseconds) and launches[k] for
- * k < nk of: 0 push+deposit, 1 hand-off (settle), 2 fold, 3 filter, 4 Yee,
- * 5 window/step bookkeeping.  Synchronises. */
+ * k < nk of: 0 push + deposit (its last block flips the particle buffers),
+ * 1 hand-off of pending leavers (settle), 2 fold, 3 filter, 4 Yee and the
+ * step end (field buffer flip, step count), 5 moving-window shift.
+ * Synchronises. */
 #define PIC_NK 6
 int pic_timing(pic_sim *sim, int enable, void *stream);
 int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void *stream);

@@ -371,8 +371,6 @@ int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
     }
     rc = timed(s, 4, st, [&] { return Launch<R>::yee(d, st); });
     if (rc) return rc;
-    rc = timed(s, 5, st, [&] { return Launch<R>::step_end(d, st); });
-    if (rc) return rc;
     if (d.window) {
         rc = enqueue_settle(s, d, st);
         if (rc) return rc;
@@ -1026,6 +1024,7 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
         b->h_batch->nwork = (int)nwork;
         b->h_batch->nsim = n;
         b->h_batch->work = b->d_work;
+        b->h_batch->blocks_done = 0;
         HIPCHK(hipMemcpyAsync(b->d_table, b->h_table, (size_t)n * sizeof(SimDev<float>),
                               hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(b->d_work, b->h_work, (size_t)nwork * sizeof(int2),

@@ -49,6 +49,7 @@ struct DevState {
     int ppar;         // particle buffer holding the tiles' particles
     int opar;         // outbox written by the last push
     int pend;         // 1: that outbox holds leavers not yet in any tile
+    int blocks_done;  // blocks of the running push launch that finished
 };
 
 // Particle hand-off between tiles.  A push reads its tile from particle
@@ -211,6 +212,7 @@ struct BatchDev {
     int nwork;        // entries of the work list in use
     int nsim;         // descriptors in use
     const int2 *work; // (simulation, tile), simulations in contiguous runs
+    int blocks_done;  // blocks of the running launch that finished
 };
 template <typename R>
 hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s);
@@ -223,7 +225,6 @@ template <typename R> struct Launch {
     static hipError_t filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
                              const R *i2, R *o0, R *o1, R *o2, hipStream_t s);
     static hipError_t yee(const SimDev<R> &d, hipStream_t s);
-    static hipError_t step_end(const SimDev<R> &d, hipStream_t s);
     static hipError_t window(const SimDev<R> &d, hipStream_t s);
     static hipError_t load(const SimDev<R> &d, int sp, hipStream_t s);
     static hipError_t rho(const SimDev<R> &d, hipStream_t s);

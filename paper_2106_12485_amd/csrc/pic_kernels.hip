@@ -702,6 +702,24 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
     }
 }
 
+// True in thread 0 of the block that finishes a launch last: every block
+// counts itself in *counter once all its threads are done; the last one
+// resets the counter for the next launch and does the launch's closing work.
+// No other block reads what that work changes (all have finished), and the
+// next launch sees it at the kernel boundary, so the count needs no ordering
+// beyond atomicity: relaxed device-scope atomics, which on this GPU do not
+// write back or invalidate the XCD's L2 as acquire/release ones would.
+__device__ __forceinline__ bool last_block(int *counter)
+{
+    __syncthreads();
+    if (threadIdx.x != 0) return false;
+    const int prev = __hip_atomic_fetch_add(glob(counter), 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (prev != (int)gridDim.x - 1) return false;
+    __hip_atomic_store(glob(counter), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // end of step: flip the field buffers, count the step and decide the window
 // shift (the window advances one cell once iter*dt >= (nshift+1)*dx, in double)
@@ -1155,6 +1173,7 @@ __global__ __launch_bounds__(NTP) __attribute__((amdgpu_waves_per_eu(PushWaves<R
 k_push_deposit(SimDev<R> d)
 {
     push_body<NTP>(d, xcd_remap(blockIdx.x, gridDim.x));
+    if (last_block(&d.st->blocks_done)) push_end_body(d);
 }
 
 template <typename R>
@@ -1164,19 +1183,8 @@ k_push_deposit_b(const SimDev<R> *__restrict__ ds,
 {
     int2 it;
     if (batch_item(b, &it)) push_body<NTB>(ds[it.x], it.y);
-}
-
-template <typename R>
-__global__ void k_push_end(SimDev<R> d)
-{
-    if (threadIdx.x == 0) push_end_body(d);
-}
-
-template <typename R>
-__global__ void k_push_end_b(const SimDev<R> *__restrict__ ds,
-                                             const BatchDev *__restrict__ b)
-{
-    for (int i = threadIdx.x; i < b->nsim; i += blockDim.x) push_end_body(ds[i]);
+    if (last_block(&const_cast<BatchDev *>(b)->blocks_done))
+        for (int i = 0; i < b->nsim; ++i) push_end_body(ds[i]);
 }
 
 template <typename R>
@@ -1219,6 +1227,14 @@ __global__ __launch_bounds__(NT) void k_yee(SimDev<R> d)
     yee_body(d, xcd_remap(blockIdx.x, gridDim.x));
 }
 
+// A Yee launch is short, so its blocks' completion counts would pile up on one
+// address; the step end runs as a one-thread launch instead.
+template <typename R>
+__global__ void k_step_end(SimDev<R> d)
+{
+    if (threadIdx.x == 0) step_end_body(d);
+}
+
 template <typename R>
 __global__ __launch_bounds__(NT) void k_yee_b(const SimDev<R> *__restrict__ ds,
                                              const BatchDev *__restrict__ b)
@@ -1228,14 +1244,7 @@ __global__ __launch_bounds__(NT) void k_yee_b(const SimDev<R> *__restrict__ ds,
 }
 
 template <typename R>
-__global__ void k_step_end(SimDev<R> d)
-{
-    if (threadIdx.x == 0) step_end_body(d);
-}
-
-template <typename R>
-__global__ void k_step_end_b(const SimDev<R> *__restrict__ ds,
-                                             const BatchDev *__restrict__ b)
+__global__ void k_step_end_b(const SimDev<R> *__restrict__ ds, const BatchDev *__restrict__ b)
 {
     for (int i = threadIdx.x; i < b->nsim; i += blockDim.x) step_end_body(ds[i]);
 }
@@ -1247,9 +1256,6 @@ template <typename R>
 hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NTP), 0, s, d);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_push_end<R>, dim3(1), dim3(64), 0, s, d);
     return hipGetLastError();
 }
 
@@ -1285,12 +1291,8 @@ template <typename R>
 hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_yee<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t Launch<R>::step_end(const SimDev<R> &d, hipStream_t s)
-{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_step_end<R>, dim3(1), dim3(64), 0, s, d);
     return hipGetLastError();
 }
@@ -1352,7 +1354,6 @@ template <typename R>
 hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_push_deposit_b<R>, dim3(grid), dim3(NTB), 0, s, ds, b);
-    hipLaunchKernelGGL(k_push_end_b<R>, dim3(1), dim3(64), 0, s, ds, b);
     hipLaunchKernelGGL(k_fold_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
     hipLaunchKernelGGL(k_filter_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
     hipLaunchKernelGGL(k_yee_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
