@@ -105,3 +105,12 @@ def test_binding_fails_loudly_without_a_gpu():
     from paper_2106_12485_amd import Simulation
     with pytest.raises(RuntimeError):
         Simulation(thermal64())
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
