@@ -120,11 +120,23 @@ def lwfa8000() -> Workload:
                 x_plasma=-1e300, seed=SEED_BASE + 4, name="lwfa_8000x512")
 
 
+def weibel512() -> Workload:
+    """Electron and positron clouds streaming along +-z through each other
+    (Weibel instability): 512^2 periodic cells of 0.1, 16 x 16 particles per
+    cell per species (134,217,728 particles), u_fl,z = +-0.6, u_th = 0.1."""
+    L = 51.2
+    return Workload("weibel_512x512", 512, 512, L, L, 0.07, 500,
+                    [SpeciesSpec(-1.0, 1.0, ppc=(16, 16), uth=(0.1,) * 3, ufl=(0.0, 0.0, 0.6)),
+                     SpeciesSpec(1.0, 1.0, ppc=(16, 16), uth=(0.1,) * 3, ufl=(0.0, 0.0, -0.6))],
+                    seed=SEED_BASE + 5)
+
+
 WORKLOADS = {
     "thermal_64x64": thermal64,
     "lwfa_2000x256": lwfa,
     "clouds_1024x1024": clouds1024,
     "lwfa_8000x512": lwfa8000,
+    "weibel_512x512": weibel512,
 }
 
 

@@ -8,7 +8,7 @@ import re
 
 import pytest
 
-from inputs import clouds1024, lwfa, lwfa8000, thermal64
+from inputs import clouds1024, lwfa, lwfa8000, thermal64, weibel512
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pic.h")
@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol(libpic):
 
 def test_mem_bytes_of_the_workloads(libpic):
     from paper_2106_12485_amd import mem_bytes
-    for w in (thermal64(), lwfa(), clouds1024(), lwfa8000()):
+    for w in (thermal64(), lwfa(), clouds1024(), lwfa8000(), weibel512()):
         n = mem_bytes(w)
         # at least the particle state of the initial load
         assert n > w.n_particles_initial() * 24

@@ -6,12 +6,14 @@ the six field planes and the particle set after one step.  Tolerance: relative
 L2 <= 1e-5 per quantity for the FP32 path, 1e-11 for the FP64 path.
 """
 import math
+import os
 import zlib
 
 import numpy as np
 import pytest
 
-from inputs import LaserSpec, SpeciesSpec, Workload, clouds1024, lwfa, random_particles, thermal64
+from inputs import (LaserSpec, SpeciesSpec, Workload, clouds1024, lwfa, random_particles,
+                    thermal64, weibel512)
 from parity_util import (TOL_STEP_FP32, TOL_STEP_FP64, add_species, compare_particles,
                          oracle_from_workload, oracle_mirror, rel_l2, round_to_f32)
 
@@ -290,6 +292,7 @@ def _full_size_parity(w, nsteps):
     sim.step(nsteps)
     assert sim.status() == 0
     om = oracle_mirror(sim, w)
+    om.set_threads(min(16, os.cpu_count() or 1))
     step_both(sim, om)
     return compare_state(sim, om, w, False, w.name)
 
@@ -304,3 +307,11 @@ def test_lwfa_2000x256_full_size_teacher_forced():
     w = lwfa()
     errs = _full_size_parity(w, 12)
     assert errs["F"] < TOL_STEP_FP32
+
+
+@pytest.mark.timeout(900)
+def test_weibel_512_full_size_teacher_forced():
+    # electron and positron clouds, 256 particles per cell each (134M particles)
+    w = weibel512()
+    errs = _full_size_parity(w, 3)
+    assert errs["J"] < TOL_STEP_FP32
