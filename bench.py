@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="clouds_1024x1024")
+    ap.add_argument("--deposit", default="reduction", choices=("reduction", "commutative"),
+                    help="how tiles' currents are combined: per-tile blocks summed by a fold "
+                         "launch, or four checkerboard colours adding straight into J")
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
@@ -201,7 +204,7 @@ def main():
         print(json.dumps(serving_leg(args.serve_requests, args.budget_gb)))
         return
     w = WORKLOADS[args.workload]()
-    sim = Simulation(w, fp64=args.fp64)
+    sim = Simulation(w, fp64=args.fp64, deposit=args.deposit)
     nparts = sum(sim.count(k) for k in range(len(w.species)))
     stream = sim.stream
 
@@ -252,11 +255,11 @@ def main():
         config=dict(workload=w.name, cells="%dx%d" % (w.nx, w.ny), particles=int(nparts),
                     species=len(w.species), ppc_per_species=w.species[0].ppc[0] *
                     w.species[0].ppc[1], dt=w.dt, filter_passes=w.filter_passes,
-                    moving_window=w.moving_window),
+                    moving_window=w.moving_window, deposit=args.deposit),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=(None if args.workload != "clouds_1024x1024" or args.fp64
-                               else measured_traffic()),
+                               or args.deposit != "reduction" else measured_traffic()),
                       kernel="k_push_deposit", avg_launch_ms=round(avg_push_s * 1e3, 4),
                       alg_bytes_per_launch=int(alg_bytes),
                       pushes_per_s_kernel=nparts / avg_push_s),

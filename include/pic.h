@@ -114,6 +114,15 @@ typedef struct {
     int load;            /* 1: load every species at init, 0: start empty */
     double capacity_factor; /* particle slots per tile = factor * ppc * 256
                                (0 selects 3.0) */
+    int deposit_mode;    /* how the tiles' currents are combined (the paper's
+                            two strategies, Sec. 3.2):
+                            0 "reduction": each tile deposits into a block of
+                              its own and a fold launch sums the blocks;
+                            1 "commutative": tiles in four checkerboard
+                              colours, one colour per launch, add their
+                              current straight into J, no two neighbours at
+                              once; no fold.  Needs a periodic box with an
+                              even number of 16-cell tiles along each axis. */
 } pic_cfg;
 
 /* Diagnostics in FP64 (stage a9).  Energies are integrals over the box:
@@ -295,8 +304,9 @@ typedef struct {
  * while the running set keeps stepping, stepped with the running set in
  * lockstep chunks of at most chunk_steps (shared launches, pic_batch_step; a
  * set of one runs its own step graph), and retired when done, freeing its
- * memory.  One at a time (batched = 0) runs the requests alone, in arrival
- * order.  out[i] receives request i's times and final diagnostics.  step_ms
+ * memory.  Batched serving takes FP32 periodic requests with the reduction
+ * deposit; others end with PIC_E_ARG.  One at a time (batched = 0) runs the
+ * requests alone, in arrival order.  out[i] receives request i's times and final diagnostics.  step_ms
  * (capacity cap_steps, may be NULL) receives the time per step of every chunk
  * and *n_steps their number.  The call returns when all its device work is
  * done.  Returns PIC_OK or the first host-side error. */

@@ -84,6 +84,11 @@ int layout(const pic_cfg *c, Layout *L)
     L->nxs = c->moving_window ? ((c->nx + TX + 2 + TX - 1) / TX) * TX : c->nx;
     L->ntx = (L->nxs + TX - 1) / TX;
     L->nty = (c->ny + TY - 1) / TY;
+    if (c->deposit_mode != 0 && c->deposit_mode != 1)
+        return fail(PIC_E_ARG, "deposit_mode must be 0 (reduction) or 1 (commutative)");
+    if (c->deposit_mode == 1 && (c->moving_window || (L->ntx & 1) || (L->nty & 1)))
+        return fail(PIC_E_ARG, "the commutative deposit needs a periodic box with an even "
+                               "number of 16-cell tiles along each axis");
     L->ntiles = L->ntx * L->nty;
     L->rs = c->fp64 ? 8 : 4;
     L->plane = (size_t)L->nxs * c->ny;
@@ -149,6 +154,7 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->cap_out = L.cap_out;
     d->npass = c->filter_passes;
     d->compensate = c->filter_compensate ? 1 : 0;
+    d->direct = c->deposit_mode == 1 ? 1 : 0;
     d->dx_d = c->lx / c->nx;
     d->dy_d = c->ly / c->ny;
     d->dt_d = c->dt;
@@ -361,8 +367,11 @@ int enqueue_deposit(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 template <typename R>
 int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
-    int rc = timed(s, 2, st, [&] { return Launch<R>::fold(d, 3, d.J[0], d.J[1], d.J[2], st); });
-    if (rc) return rc;
+    int rc = PIC_OK;
+    if (!d.direct) {
+        rc = timed(s, 2, st, [&] { return Launch<R>::fold(d, 3, d.J[0], d.J[1], d.J[2], st); });
+        if (rc) return rc;
+    }
     if (d.npass > 0) {
         rc = timed(s, 3, st, [&] {
             return Launch<R>::filter(d, 3, d.J[0], d.J[1], d.J[2], d.Jf[0], d.Jf[1], d.Jf[2], st);
@@ -1009,8 +1018,9 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
         long long nwork = 0;
         for (int i = 0; i < n; ++i) {
             const pic_sim *s = sims[i];
-            if (!s || s->cfg.fp64 || s->cfg.moving_window)
-                return fail(PIC_E_ARG, "batches hold FP32 periodic simulations only");
+            if (!s || s->cfg.fp64 || s->cfg.moving_window || s->cfg.deposit_mode != 0)
+                return fail(PIC_E_ARG, "batches hold FP32 periodic simulations with the "
+                                       "reduction deposit only");
             nwork += s->L.ntiles;
         }
         if (nwork > b->max_tiles) return fail(PIC_E_ARG, "batch work list too long");
@@ -1177,8 +1187,11 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
         for (size_t qi = 0; qi < queue.size() && (int)active.size() < max_active;) {
             const int r = queue[qi];
             const size_t need = pic_mem_bytes(&reqs[r].cfg);
-            if (need == 0 || align256(need) > pool_bytes) {
-                out[r].status = need == 0 ? PIC_E_ARG : PIC_E_NOMEM;
+            const bool unbatchable = opts->batched && (reqs[r].cfg.fp64 ||
+                                                       reqs[r].cfg.moving_window ||
+                                                       reqs[r].cfg.deposit_mode != 0);
+            if (need == 0 || unbatchable || align256(need) > pool_bytes) {
+                out[r].status = need == 0 || unbatchable ? PIC_E_ARG : PIC_E_NOMEM;
                 ++done;
                 queue.erase(queue.begin() + qi);
                 continue;

@@ -94,6 +94,7 @@ struct SimDev {
     int ntx, nty, ntiles;
     int window, nsp, cap_out;
     int npass, compensate;
+    int direct;       // 1: colour-phased deposit straight into J (no fold)
     R dx, dy, dt;
     R idx, idy;       // 1/dx, 1/dy
     R dt_dx, dt_dy;   // dt/dx, dt/dy

@@ -192,7 +192,7 @@ __device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R
 // wavefront, and the ones that leave go to outbox opar ^ 1 with their
 // direction.  Particles leaving the moving window are dropped.
 // ---------------------------------------------------------------------------
-template <int BT, typename R>
+template <int BT, bool DIRECT, typename R>
 __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
 {
     __shared__ R sf[6 * BP];
@@ -407,9 +407,22 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
         __syncthreads();
     }
     // one flush of the tile's current block per step
-    const gptr<R> out = glob(d.blk + (size_t)t * 3 * BP);
     const double jqi = d.jq_inv;
-    for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = (R)fx_value(sj[k], jqi);
+    if (DIRECT) {
+        // add the block into J: no other tile of this launch's colour touches
+        // these cells (same-colour tiles are two tiles apart)
+        for (int k = threadIdx.x; k < 3 * BP; k += BT) {
+            const int c = k / BP, kk = k - c * BP;
+            const int lx = kk % PX - 1, ly = kk / PX - 1;
+            if (lx >= w + 2 || ly >= h + 2) continue;  // beyond a ragged tile's guards
+            const size_t g = (size_t)wrapi(x0 + lx, d.nxs) + (size_t)wrapi(y0 + ly, d.ny) * d.nxs;
+            const gptr<R> J = glob(d.J[c]);
+            J[g] = J[g] + (R)fx_value(sj[k], jqi);
+        }
+    } else {
+        const gptr<R> out = glob(d.blk + (size_t)t * 3 * BP);
+        for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = (R)fx_value(sj[k], jqi);
+    }
 }
 
 // After each push: both buffers flip and its outbox is pending.
@@ -1172,7 +1185,7 @@ template <typename R>
 __global__ __launch_bounds__(NTP) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
 k_push_deposit(SimDev<R> d)
 {
-    push_body<NTP>(d, xcd_remap(blockIdx.x, gridDim.x));
+    push_body<NTP, false>(d, xcd_remap(blockIdx.x, gridDim.x));
     if (last_block(&d.st->blocks_done)) push_end_body(d);
 }
 
@@ -1182,9 +1195,36 @@ k_push_deposit_b(const SimDev<R> *__restrict__ ds,
                                              const BatchDev *__restrict__ b)
 {
     int2 it;
-    if (batch_item(b, &it)) push_body<NTB>(ds[it.x], it.y);
+    if (batch_item(b, &it)) push_body<NTB, false>(ds[it.x], it.y);
     if (last_block(&const_cast<BatchDev *>(b)->blocks_done))
         for (int i = 0; i < b->nsim; ++i) push_end_body(ds[i]);
+}
+
+// The commutative deposit: one launch per checkerboard colour (tiles with
+// tx % 2 == colour & 1 and ty % 2 == colour >> 1) adds its tiles' current
+// straight into J; the launch of the last colour flips the particle buffers.
+template <typename R>
+__global__ __launch_bounds__(NTP) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
+k_push_colour(SimDev<R> d, int colour)
+{
+    const int hx = d.ntx >> 1;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = 2 * (i % hx) + (colour & 1), ty = 2 * (i / hx) + (colour >> 1);
+    push_body<NTP, true>(d, tx + ty * d.ntx);
+    if (last_block(&d.st->blocks_done) && colour == 3) push_end_body(d);
+}
+
+// J = 0 on the three planes before the first colour
+template <typename R>
+__global__ __launch_bounds__(NT) void k_zero_j(SimDev<R> d)
+{
+    const long long n = (long long)d.nxs * d.ny;
+    for (long long g = blockIdx.x * (long long)NT + threadIdx.x; g < n;
+         g += (long long)gridDim.x * NT) {
+        glob(d.J[0])[g] = R(0);
+        glob(d.J[1])[g] = R(0);
+        glob(d.J[2])[g] = R(0);
+    }
 }
 
 template <typename R>
@@ -1255,6 +1295,15 @@ __global__ void k_step_end_b(const SimDev<R> *__restrict__ ds, const BatchDev *_
 template <typename R>
 hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 {
+    if (d.direct) {
+        hipLaunchKernelGGL(k_zero_j<R>, dim3(512), dim3(NT), 0, s, d);
+        hipError_t e = hipGetLastError();
+        for (int colour = 0; colour < 4 && e == hipSuccess; ++colour) {
+            hipLaunchKernelGGL(k_push_colour<R>, dim3(d.ntiles / 4), dim3(NTP), 0, s, d, colour);
+            e = hipGetLastError();
+        }
+        return e;
+    }
     hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NTP), 0, s, d);
     return hipGetLastError();
 }

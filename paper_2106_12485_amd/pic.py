@@ -39,7 +39,8 @@ class Cfg(C.Structure):
                 ("dt", C.c_double), ("moving_window", C.c_int), ("filter_passes", C.c_int),
                 ("filter_compensate", C.c_int), ("n_species", C.c_int),
                 ("sp", SpeciesCfg * MAX_SPECIES), ("laser", LaserCfg), ("fp64", C.c_int),
-                ("seed", C.c_ulonglong), ("load", C.c_int), ("capacity_factor", C.c_double)]
+                ("seed", C.c_ulonglong), ("load", C.c_int), ("capacity_factor", C.c_double),
+                ("deposit_mode", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -148,7 +149,10 @@ def _check(rc):
     return rc
 
 
-def make_cfg(w, fp64=False, load=True, capacity_factor=0.0) -> Cfg:
+DEPOSIT_MODES = {"reduction": 0, "commutative": 1}
+
+
+def make_cfg(w, fp64=False, load=True, capacity_factor=0.0, deposit="reduction") -> Cfg:
     """Fill the C configuration from a workload description (any object with
     nx, ny, lx, ly, dt, species, moving_window, filter_passes,
     filter_compensate, laser, seed attributes)."""
@@ -182,11 +186,12 @@ def make_cfg(w, fp64=False, load=True, capacity_factor=0.0) -> Cfg:
     c.seed = int(getattr(w, "seed", 0)) & 0xFFFFFFFFFFFFFFFF
     c.load = int(bool(load))
     c.capacity_factor = float(capacity_factor)
+    c.deposit_mode = DEPOSIT_MODES[deposit]
     return c
 
 
-def mem_bytes(w, fp64=False, capacity_factor=0.0) -> int:
-    cfg = make_cfg(w, fp64=fp64, capacity_factor=capacity_factor)
+def mem_bytes(w, fp64=False, capacity_factor=0.0, deposit="reduction") -> int:
+    cfg = make_cfg(w, fp64=fp64, capacity_factor=capacity_factor, deposit=deposit)
     n = lib().pic_mem_bytes(C.byref(cfg))
     if n == 0:
         raise PicError(PIC_E_ARG, lib().pic_last_error().decode())
@@ -205,12 +210,13 @@ class Simulation:
     """One simulation resident in a device arena owned by this object."""
 
     def __init__(self, w, fp64=False, load=True, capacity_factor=0.0, device="cuda",
-                 stream=None, arena=None):
+                 stream=None, arena=None, deposit="reduction"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libpic needs a GPU; none is visible")
         L = lib()
-        self.cfg = make_cfg(w, fp64=fp64, load=load, capacity_factor=capacity_factor)
+        self.cfg = make_cfg(w, fp64=fp64, load=load, capacity_factor=capacity_factor,
+                            deposit=deposit)
         self.nx, self.ny = self.cfg.nx, self.cfg.ny
         self.n_species = self.cfg.n_species
         nbytes = L.pic_mem_bytes(C.byref(self.cfg))

@@ -79,6 +79,12 @@ def test_validation_rejects_bad_configurations(libpic):
     c = pic.make_cfg(w)
     c.sp[0].ppc_x = 0
     assert libpic.pic_mem_bytes(C.byref(c)) == 0
+    # the commutative deposit needs an even number of tiles per axis, periodic
+    assert "commutative" in bad(deposit_mode=1, nx=48, lx=4.8)
+    assert "commutative" in bad(deposit_mode=1, moving_window=1)
+    assert "deposit_mode" in bad(deposit_mode=2)
+    c = pic.make_cfg(w, deposit="commutative")
+    assert libpic.pic_mem_bytes(C.byref(c)) > 0
 
 
 def test_init_error_codes_before_any_device_work(libpic):

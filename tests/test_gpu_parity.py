@@ -63,8 +63,10 @@ def random_state(w, rng, uth=0.4, famp=0.2, n_per_species=None):
     return parts, f
 
 
-def setup_pair(w, parts, f, fp64=False, it=0, nshift=0, capacity_factor=0.0):
-    sim = Simulation(w, fp64=fp64, load=False, capacity_factor=capacity_factor)
+def setup_pair(w, parts, f, fp64=False, it=0, nshift=0, capacity_factor=0.0,
+               deposit="reduction"):
+    sim = Simulation(w, fp64=fp64, load=False, capacity_factor=capacity_factor,
+                     deposit=deposit)
     o = oracle_from_workload(w)
     add_species(o, w, load=False)
     for k, p in enumerate(parts):
@@ -285,8 +287,8 @@ def test_lwfa_window_run_counts_and_teacher_forced_shift():
     assert abs(sim.count(0) - o.count(0)) <= 8
 
 
-def _full_size_parity(w, nsteps):
-    sim = Simulation(w)
+def _full_size_parity(w, nsteps, deposit="reduction"):
+    sim = Simulation(w, deposit=deposit)
     n0 = sim.count(0)
     assert n0 > 0
     sim.step(nsteps)
@@ -314,4 +316,50 @@ def test_weibel_512_full_size_teacher_forced():
     # electron and positron clouds, 256 particles per cell each (134M particles)
     w = weibel512()
     errs = _full_size_parity(w, 3)
+    assert errs["J"] < TOL_STEP_FP32
+
+
+# ---------------------------------------------------------------------------
+# the commutative deposit: four checkerboard colours add straight into J
+# ---------------------------------------------------------------------------
+COMMUTATIVE_CASES = {
+    # name: (workload, fp64); even tile counts, ragged last tiles
+    "ragged_56x56_comp": (two_species(56, 56, 5.6, 5.6, filter_passes=1, filter_compensate=True),
+                          False),
+    "two_tiles_24x32": (two_species(24, 32, 2.4, 3.2, filter_passes=1), False),
+    "fp64_64x32": (two_species(64, 32, 6.4, 3.2, filter_passes=2), True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(COMMUTATIVE_CASES))
+def test_commutative_deposit_one_step_matches_oracle(name):
+    w, fp64 = COMMUTATIVE_CASES[name]
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    parts, f = random_state(w, rng)
+    sim, o = setup_pair(w, parts, f, fp64=fp64, deposit="commutative")
+    step_both(sim, o)
+    compare_state(sim, o, w, fp64, name)
+    assert sim.status() == 0
+
+
+def test_commutative_deposit_migration_then_teacher_forced_step():
+    w = two_species(56, 56, 5.6, 5.6, filter_passes=1, filter_compensate=True)
+    rng = np.random.default_rng(21)
+    parts, f = random_state(w, rng)
+    sim, _ = setup_pair(w, parts, f, deposit="commutative")
+    a, _ = setup_pair(w, parts, f, deposit="commutative")
+    sim.step(15)
+    for _ in range(15):
+        a.deposit()
+        a.field_advance()
+    # colour order is fixed, so graph replay and direct launches agree bitwise
+    assert np.array_equal(sim.get_fields(), a.get_fields())
+    assert [sim.count(k) for k in range(2)] == [len(p["ix"]) for p in parts]
+    om = oracle_mirror(sim, w)
+    step_both(sim, om)
+    compare_state(sim, om, w, False, "commutative after 15 steps")
+
+
+def test_clouds_1024_commutative_full_size_teacher_forced():
+    errs = _full_size_parity(clouds1024(), 5, deposit="commutative")
     assert errs["J"] < TOL_STEP_FP32
