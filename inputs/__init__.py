@@ -120,6 +120,13 @@ def lwfa8000() -> Workload:
                 x_plasma=-1e300, seed=SEED_BASE + 4, name="lwfa_8000x512")
 
 
+def lwfa2000x512() -> Workload:
+    """The paper's LWFA size: 2000x512 cells, 16 ppc, 4000 steps, with the
+    cell size and step of the 2000x256 run (box 40 x 102.4)."""
+    return lwfa(nx=2000, ny=512, lx=40.0, ly=102.4, dt=0.014, ppc=(4, 4), steps=4000,
+                seed=SEED_BASE + 6, name="lwfa_2000x512")
+
+
 def weibel512() -> Workload:
     """Electron and positron clouds streaming along +-z through each other
     (Weibel instability): 512^2 periodic cells of 0.1, 16 x 16 particles per
@@ -137,6 +144,7 @@ WORKLOADS = {
     "clouds_1024x1024": clouds1024,
     "lwfa_8000x512": lwfa8000,
     "weibel_512x512": weibel512,
+    "lwfa_2000x512": lwfa2000x512,
 }
 
 

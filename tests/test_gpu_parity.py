@@ -12,8 +12,8 @@ import zlib
 import numpy as np
 import pytest
 
-from inputs import (LaserSpec, SpeciesSpec, Workload, clouds1024, lwfa, random_particles,
-                    thermal64, weibel512)
+from inputs import (LaserSpec, SpeciesSpec, Workload, clouds1024, lwfa, lwfa2000x512,
+                    random_particles, thermal64, weibel512)
 from parity_util import (TOL_STEP_FP32, TOL_STEP_FP64, add_species, compare_particles,
                          oracle_from_workload, oracle_mirror, rel_l2, round_to_f32)
 
@@ -363,3 +363,22 @@ def test_commutative_deposit_migration_then_teacher_forced_step():
 def test_clouds_1024_commutative_full_size_teacher_forced():
     errs = _full_size_parity(clouds1024(), 5, deposit="commutative")
     assert errs["J"] < TOL_STEP_FP32
+
+
+@pytest.mark.timeout(900)
+def test_lwfa_2000x512_paper_scale_run():
+    # the paper's LWFA size, all 4000 steps, then a teacher-forced step
+    w = lwfa2000x512()
+    sim = Simulation(w)
+    sim.step(w.steps)
+    e = sim.energy()
+    assert e["status"] == 0 and e["step"] == w.steps
+    assert e["nshift"] == int(w.steps * w.dt / w.dx + 1e-9)
+    # the window has left the vacuum behind: plasma (16 per cell) fills the box,
+    # up to the particles the wake moved across the window's edges
+    full = w.nx * w.ny * 16
+    assert 0.95 * full < e["n_particles"][0] < 1.02 * full
+    om = oracle_mirror(sim, w)
+    om.set_threads(min(16, os.cpu_count() or 1))
+    step_both(sim, om)
+    compare_state(sim, om, w, False, w.name)
