@@ -221,7 +221,8 @@ hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, h
 // Launchers (defined in pic_kernels.hip for R = float and double).
 template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
-    static hipError_t settle(const SimDev<R> &d, hipStream_t s);
+    // only_if_shift: skip unless the last step shifted the moving window
+    static hipError_t settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift = false);
     static hipError_t fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s);
     static hipError_t filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
                              const R *i2, R *o0, R *o1, R *o2, hipStream_t s);

@@ -441,11 +441,12 @@ __device__ __forceinline__ void push_end_body(const SimDev<R> &d)
 constexpr int MT = 64;
 
 template <typename R>
-__global__ __launch_bounds__(MT) void k_settle(SimDev<R> d)
+__global__ __launch_bounds__(MT) void k_settle(SimDev<R> d, int only_if_shift)
 {
     __shared__ int s_nb[N_DIR], s_len[N_DIR];
     __shared__ unsigned char s_want[N_DIR];
     const DevState *st = d.st;
+    if (only_if_shift && !st->shift) return;
     if (!st->pend) return;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int pp = st->ppar, ob = st->opar;
@@ -495,9 +496,9 @@ __global__ __launch_bounds__(MT) void k_settle(SimDev<R> d)
 }
 
 template <typename R>
-__global__ void k_unpend(SimDev<R> d)
+__global__ void k_unpend(SimDev<R> d, int only_if_shift)
 {
-    if (threadIdx.x == 0) d.st->pend = 0;
+    if (threadIdx.x == 0 && !(only_if_shift && !d.st->shift)) d.st->pend = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1309,14 +1310,14 @@ hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 }
 
 template <typename R>
-hipError_t Launch<R>::settle(const SimDev<R> &d, hipStream_t s)
+hipError_t Launch<R>::settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift)
 {
     if (d.nsp > 0) {
-        hipLaunchKernelGGL(k_settle<R>, dim3(d.ntiles), dim3(MT), 0, s, d);
+        hipLaunchKernelGGL(k_settle<R>, dim3(d.ntiles), dim3(MT), 0, s, d, (int)only_if_shift);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_unpend<R>, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_unpend<R>, dim3(1), dim3(64), 0, s, d, (int)only_if_shift);
     return hipGetLastError();
 }
 
