@@ -550,16 +550,23 @@ __device__ __forceinline__ void fold_body(const SimDev<R> &d, const int t, int n
 
 // ---------------------------------------------------------------------------
 // row a6: binomial filter.  Per tile: load the planes with a halo of
-// npass + compensate cells, apply the x passes (binomial, then compensator),
-// then the y passes, keeping the gap at zero; write the interior.
+// rf = npass + compensate cells, apply the x passes (binomial, then
+// compensator), then the y passes, keeping the gap at zero; write the
+// interior.  All planes go through each pass together.  A pass only touches
+// the rows of the halo'd tile, the x passes its halo'd columns and the y
+// passes the tile's own.  Cells next to that region are never written, so
+// the region's rim takes arbitrary values, but after rf passes these have
+// moved at most rf - 1 cells inwards and never reach the interior.
 // ---------------------------------------------------------------------------
+constexpr int QB = QX * QY; // cells of one plane's filter block
+
 template <typename R>
 __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int nplanes,
                                             const R *i0, const R *i1, const R *i2, R *o0,
                                             R *o1, R *o2)
 {
-    __shared__ R sa[QX * QY];
-    __shared__ R sb[QX * QY];
+    __shared__ R sa[3 * QB];
+    __shared__ R sb[3 * QB];
     __shared__ unsigned char s_gap[QX];
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
@@ -567,64 +574,69 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
     const int origin = glob(d.st)->origin;
     const int rf = d.npass + (d.compensate ? 1 : 0);
     const R N = (R)d.npass;
+    const gptr<const R> in[3] = {glob(i0), glob(i1), glob(i2)};
     for (int k = threadIdx.x; k < QX; k += NT) {
         int gx = (x0 + k - MAX_FR) % d.nxs;
         gx += gx < 0 ? d.nxs : 0;
         s_gap[k] = d.window && window_col(gx, origin, d.nxs) >= d.nx;
     }
-    for (int pl = 0; pl < nplanes; ++pl) {
-        const gptr<const R> in = glob(pl == 0 ? i0 : (pl == 1 ? i1 : i2));
-        const gptr<R> out = glob(pl == 0 ? o0 : (pl == 1 ? o1 : o2));
+    // rows [MAX_FR - rf, MAX_FR + h + rf) of the block hold the halo'd tile;
+    // its columns are [MAX_FR - rf, MAX_FR + w + rf)
+    const int k0 = (MAX_FR - rf) * QX, k1 = (MAX_FR + h + rf) * QX;
+    const int ilo = MAX_FR - rf, ihi = MAX_FR + w + rf;
+    for (int k = k0 + threadIdx.x; k < k1; k += NT) {
+        const int i = k % QX, j = k / QX;
+        if (i < ilo || i >= ihi) continue;
+        // the halo may reach beyond one period on tiny grids
+        int gx = (x0 + i - MAX_FR) % d.nxs;
+        gx += gx < 0 ? d.nxs : 0;
+        int gy = (y0 + j - MAX_FR) % d.ny;
+        gy += gy < 0 ? d.ny : 0;
+        const size_t g = (size_t)gx + (size_t)gy * d.nxs;
+        for (int pl = 0; pl < nplanes; ++pl) sa[pl * QB + k] = in[pl][g];
+    }
+    __syncthreads();
+    R *a = sa, *b = sb;
+    for (int pass = 0; pass < rf; ++pass) {
+        const bool comp = pass == d.npass;
+        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+        for (int k = k0 + threadIdx.x; k < k1; k += NT) {
+            const int i = k % QX;
+            if (i < ilo || i >= ihi) continue;
+            const bool live = i > 0 && i < QX - 1 && !s_gap[i];
+            for (int pl = 0; pl < nplanes; ++pl) {
+                const int q = pl * QB + k;
+                b[q] = live ? w0 * a[q - 1] + w1 * a[q] + w0 * a[q + 1] : R(0);
+            }
+        }
         __syncthreads();
-        for (int k = threadIdx.x; k < QX * QY; k += NT) {
-            const int lx = k % QX - MAX_FR, ly = k / QX - MAX_FR;
-            R v = R(0);
-            if (lx >= -rf && lx < w + rf && ly >= -rf && ly < h + rf) {
-                // the halo may reach beyond one period on tiny grids
-                int gx = (x0 + lx) % d.nxs;
-                gx += gx < 0 ? d.nxs : 0;
-                int gy = (y0 + ly) % d.ny;
-                gy += gy < 0 ? d.ny : 0;
-                v = in[(size_t)gx + (size_t)gy * d.nxs];
+        R *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    for (int pass = 0; pass < rf; ++pass) {
+        const bool comp = pass == d.npass;
+        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+        for (int k = k0 + threadIdx.x; k < k1; k += NT) {
+            const int i = k % QX, j = k / QX;
+            if (i < MAX_FR || i >= MAX_FR + w) continue;
+            const bool live = j > 0 && j < QY - 1;
+            for (int pl = 0; pl < nplanes; ++pl) {
+                const int q = pl * QB + k;
+                b[q] = live ? w0 * a[q - QX] + w1 * a[q] + w0 * a[q + QX] : R(0);
             }
-            sa[k] = v;
-            sb[k] = R(0);
         }
         __syncthreads();
-        R *a = sa, *b = sb;
-        for (int pass = 0; pass < rf; ++pass) {
-            const bool comp = pass == d.npass;
-            const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
-            for (int k = threadIdx.x; k < QX * QY; k += NT) {
-                const int i = k % QX;
-                R v = R(0);
-                if (i > 0 && i < QX - 1 && !s_gap[i]) v = w0 * a[k - 1] + w1 * a[k] + w0 * a[k + 1];
-                b[k] = v;
-            }
-            __syncthreads();
-            R *tmp = a;
-            a = b;
-            b = tmp;
-        }
-        for (int pass = 0; pass < rf; ++pass) {
-            const bool comp = pass == d.npass;
-            const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
-            for (int k = threadIdx.x; k < QX * QY; k += NT) {
-                const int j = k / QX;
-                R v = R(0);
-                if (j > 0 && j < QY - 1) v = w0 * a[k - QX] + w1 * a[k] + w0 * a[k + QX];
-                b[k] = v;
-            }
-            __syncthreads();
-            R *tmp = a;
-            a = b;
-            b = tmp;
-        }
-        for (int k = threadIdx.x; k < w * h; k += NT) {
-            const int lx = k % w, ly = k / w;
-            out[(size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs] =
-                a[(lx + MAX_FR) + (ly + MAX_FR) * QX];
-        }
+        R *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    R *const out[3] = {o0, o1, o2};
+    for (int k = threadIdx.x; k < w * h; k += NT) {
+        const int lx = k % w, ly = k / w;
+        const size_t g = (size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs;
+        const int q = (lx + MAX_FR) + (ly + MAX_FR) * QX;
+        for (int pl = 0; pl < nplanes; ++pl) glob(out[pl])[g] = a[pl * QB + q];
     }
 }
 
