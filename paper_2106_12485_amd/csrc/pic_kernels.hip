@@ -574,7 +574,10 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
     const int origin = glob(d.st)->origin;
     const int rf = d.npass + (d.compensate ? 1 : 0);
     const R N = (R)d.npass;
-    const gptr<const R> in[3] = {glob(i0), glob(i1), glob(i2)};
+    // a single plane (the charge) also runs through the other two slots, on
+    // a copy of itself, so that every loop below has a fixed trip count
+    const gptr<const R> in[3] = {glob(i0), glob(nplanes > 1 ? i1 : i0),
+                                 glob(nplanes > 2 ? i2 : i0)};
     for (int k = threadIdx.x; k < QX; k += NT) {
         int gx = (x0 + k - MAX_FR) % d.nxs;
         gx += gx < 0 ? d.nxs : 0;
@@ -584,16 +587,32 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
     // its columns are [MAX_FR - rf, MAX_FR + w + rf)
     const int k0 = (MAX_FR - rf) * QX, k1 = (MAX_FR + h + rf) * QX;
     const int ilo = MAX_FR - rf, ihi = MAX_FR + w + rf;
-    for (int k = k0 + threadIdx.x; k < k1; k += NT) {
+    // all loads go out before the first LDS store; a cell outside the
+    // halo'd tile reads cell 0 and is not stored
+    constexpr int FRN = (QB + NT - 1) / NT;
+    R v[FRN][3];
+    bool live[FRN];
+#pragma unroll
+    for (int r = 0; r < FRN; ++r) {
+        const int k = k0 + threadIdx.x + r * NT;
         const int i = k % QX, j = k / QX;
-        if (i < ilo || i >= ihi) continue;
+        live[r] = k < k1 && i >= ilo && i < ihi;
         // the halo may reach beyond one period on tiny grids
         int gx = (x0 + i - MAX_FR) % d.nxs;
         gx += gx < 0 ? d.nxs : 0;
         int gy = (y0 + j - MAX_FR) % d.ny;
         gy += gy < 0 ? d.ny : 0;
-        const size_t g = (size_t)gx + (size_t)gy * d.nxs;
-        for (int pl = 0; pl < nplanes; ++pl) sa[pl * QB + k] = in[pl][g];
+        const size_t g = live[r] ? (size_t)gx + (size_t)gy * d.nxs : 0;
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) v[r][pl] = in[pl][g];
+    }
+#pragma unroll
+    for (int r = 0; r < FRN; ++r) {
+        const int k = k0 + threadIdx.x + r * NT;
+        if (live[r]) {
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) sa[pl * QB + k] = v[r][pl];
+        }
     }
     __syncthreads();
     R *a = sa, *b = sb;
@@ -604,7 +623,8 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
             const int i = k % QX;
             if (i < ilo || i >= ihi) continue;
             const bool live = i > 0 && i < QX - 1 && !s_gap[i];
-            for (int pl = 0; pl < nplanes; ++pl) {
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
                 const int q = pl * QB + k;
                 b[q] = live ? w0 * a[q - 1] + w1 * a[q] + w0 * a[q + 1] : R(0);
             }
@@ -621,7 +641,8 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
             const int i = k % QX, j = k / QX;
             if (i < MAX_FR || i >= MAX_FR + w) continue;
             const bool live = j > 0 && j < QY - 1;
-            for (int pl = 0; pl < nplanes; ++pl) {
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
                 const int q = pl * QB + k;
                 b[q] = live ? w0 * a[q - QX] + w1 * a[q] + w0 * a[q + QX] : R(0);
             }
