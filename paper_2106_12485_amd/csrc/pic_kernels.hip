@@ -749,6 +749,99 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
     }
 }
 
+// Row a7 in streaming form, for one simulation: each wavefront advances a
+// strip of YS_S rows and YS_W columns.  Lane L holds column c0 + L - 1 of
+// every row, so one row of a plane is a single contiguous load of the
+// wavefront; x neighbours come from the adjacent lanes and y neighbours from
+// the rows held in registers.  All loads of the strip go out before the
+// first update.  Lane 0 (B half at i - 1) and lanes YS_W + 1, YS_W + 2 (E at
+// i + 1, i + 2) are the halo: lanes 1..YS_W end with complete results.  The
+// arithmetic is that of yee_body, term for term.
+constexpr int YS_W = 61;
+constexpr int YS_S = 8;
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
+{
+    const int ncg = (d.nxs + YS_W - 1) / YS_W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int cg = blk % ncg, r0 = (blk / ncg) * YS_S;
+    const int nr = min(YS_S, d.ny - r0);
+    const int L = threadIdx.x;
+    const int cx = cg * YS_W + L - 1;
+    int gx = cx % d.nxs;
+    gx += gx < 0 ? d.nxs : 0;
+    const bool put = L >= 1 && L <= YS_W && cx < d.nxs;
+    const int par = glob(d.st)->parity, origin = glob(d.st)->origin;
+    const bool gp = d.window && window_col(gx, origin, d.nxs) >= d.nx;
+    const R hdt = R(0.5) * d.dt;
+    auto at = [&](int j) {
+        int gy = j % d.ny;
+        gy += gy < 0 ? d.ny : 0;
+        return (size_t)gx + (size_t)gy * d.nxs;
+    };
+    // rows r0 - 1 + q: E for q in [0, YS_S + 3), B in [0, YS_S + 2), J in [1, YS_S + 2)
+    R eo[YS_S + 3][3], bo[YS_S + 2][3], jj[YS_S + 1][3];
+#pragma unroll
+    for (int q = 0; q < YS_S + 3; ++q) {
+        const size_t g = at(r0 - 1 + q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            eo[q][c] = glob<const R>(par ? d.F[1][c] : d.F[0][c])[g];
+            if (q < YS_S + 2) bo[q][c] = glob<const R>(par ? d.F[1][3 + c] : d.F[0][3 + c])[g];
+            if (q >= 1 && q < YS_S + 2) jj[q - 1][c] = glob<const R>(d.Jf[c])[g];
+        }
+    }
+    // B half step, rows r0 - 1 .. r0 + YS_S
+    R bh[YS_S + 2][3];
+#pragma unroll
+    for (int q = 0; q < YS_S + 2; ++q) {
+        const R ey1 = __shfl_down(eo[q][1], 1), ez1 = __shfl_down(eo[q][2], 1);
+        const R dEz_dy = (eo[q + 1][2] - eo[q][2]) * d.idy;
+        const R dEz_dx = (ez1 - eo[q][2]) * d.idx;
+        const R dEy_dx = (ey1 - eo[q][1]) * d.idx;
+        const R dEx_dy = (eo[q + 1][0] - eo[q][0]) * d.idy;
+        bh[q][0] = gp ? R(0) : bo[q][0] - hdt * dEz_dy;
+        bh[q][1] = gp ? R(0) : bo[q][1] + hdt * dEz_dx;
+        bh[q][2] = gp ? R(0) : bo[q][2] - hdt * (dEy_dx - dEx_dy);
+    }
+    // E full step, rows r0 .. r0 + YS_S
+    R en[YS_S + 1][3];
+#pragma unroll
+    for (int q = 1; q < YS_S + 2; ++q) {
+        const R by0 = __shfl_up(bh[q][1], 1), bz0 = __shfl_up(bh[q][2], 1);
+        const R dBz_dy = (bh[q][2] - bh[q - 1][2]) * d.idy;
+        const R dBz_dx = (bh[q][2] - bz0) * d.idx;
+        const R dBy_dx = (bh[q][1] - by0) * d.idx;
+        const R dBx_dy = (bh[q][0] - bh[q - 1][0]) * d.idy;
+        en[q - 1][0] = gp ? R(0) : eo[q][0] + d.dt * (dBz_dy - jj[q - 1][0]);
+        en[q - 1][1] = gp ? R(0) : eo[q][1] + d.dt * (-dBz_dx - jj[q - 1][1]);
+        en[q - 1][2] = gp ? R(0) : eo[q][2] + d.dt * (dBy_dx - dBx_dy - jj[q - 1][2]);
+    }
+    // B half step on the strip's rows, and write out
+    const int npar = par ^ 1;
+#pragma unroll
+    for (int m = 0; m < YS_S; ++m) {
+        const R ey1 = __shfl_down(en[m][1], 1), ez1 = __shfl_down(en[m][2], 1);
+        const R dEz_dy = (en[m + 1][2] - en[m][2]) * d.idy;
+        const R dEz_dx = (ez1 - en[m][2]) * d.idx;
+        const R dEy_dx = (ey1 - en[m][1]) * d.idx;
+        const R dEx_dy = (en[m + 1][0] - en[m][0]) * d.idy;
+        const R nbx = gp ? R(0) : bh[m + 1][0] - hdt * dEz_dy;
+        const R nby = gp ? R(0) : bh[m + 1][1] + hdt * dEz_dx;
+        const R nbz = gp ? R(0) : bh[m + 1][2] - hdt * (dEy_dx - dEx_dy);
+        if (put && m < nr) {
+            const size_t g = at(r0 + m);
+            glob(npar ? d.F[1][0] : d.F[0][0])[g] = en[m][0];
+            glob(npar ? d.F[1][1] : d.F[0][1])[g] = en[m][1];
+            glob(npar ? d.F[1][2] : d.F[0][2])[g] = en[m][2];
+            glob(npar ? d.F[1][3] : d.F[0][3])[g] = nbx;
+            glob(npar ? d.F[1][4] : d.F[0][4])[g] = nby;
+            glob(npar ? d.F[1][5] : d.F[0][5])[g] = nbz;
+        }
+    }
+}
+
 // True in thread 0 of the block that finishes a launch last: every block
 // counts itself in *counter once all its threads are done; the last one
 // resets the counter for the next launch and does the launch's closing work.
@@ -1373,7 +1466,8 @@ hipError_t Launch<R>::filter(const SimDev<R> &d, int nplanes, const R *i0, const
 template <typename R>
 hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_yee<R>, dim3(d.ntiles), dim3(NT), 0, s, d);
+    const int nstrip = ((d.nxs + YS_W - 1) / YS_W) * ((d.ny + YS_S - 1) / YS_S);
+    hipLaunchKernelGGL(k_yee_s<R>, dim3(nstrip), dim3(64), 0, s, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_step_end<R>, dim3(1), dim3(64), 0, s, d);
