@@ -565,6 +565,9 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
                                             const R *i0, const R *i1, const R *i2, R *o0,
                                             R *o1, R *o2)
 {
+    // no contraction into fma: the tile and streaming forms (and the batched
+    // launches) must round every term alike
+#pragma clang fp contract(off)
     __shared__ R sa[3 * QB];
     __shared__ R sb[3 * QB];
     __shared__ unsigned char s_gap[QX];
@@ -669,6 +672,9 @@ __device__ __forceinline__ void filter_body(const SimDev<R> &d, const int t, int
 template <typename R>
 __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
 {
+    // no contraction into fma: the tile and streaming forms (and the batched
+    // launches) must round every term alike
+#pragma clang fp contract(off)
     __shared__ R e[3 * BP];
     __shared__ R b[3 * BP];
     __shared__ R jl[3 * BP];
@@ -749,6 +755,88 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
     }
 }
 
+// Row a6 in streaming form, for the three current planes of one simulation:
+// each wavefront filters a strip of FS_S rows and 64 - 2 RF columns, where
+// RF = npass + compensate.  Lane L holds column c0 + L - RF of every row.
+// The x passes take their neighbours from the adjacent lanes, the y passes
+// from the rows held in registers.  The outermost lanes and rows take
+// arbitrary values that move one cell inwards per pass, so after RF passes
+// lanes [RF, 64 - RF) and rows [RF, FS_S + RF) are exact.  Same arithmetic
+// as filter_body, term for term.
+constexpr int FS_S = 8;
+
+template <typename R, int RF>
+__global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const R *i1,
+                                                const R *i2, R *o0, R *o1, R *o2)
+{
+    // no contraction into fma: the tile and streaming forms (and the batched
+    // launches) must round every term alike
+#pragma clang fp contract(off)
+    constexpr int W = 64 - 2 * RF, NRW = FS_S + 2 * RF;
+    const int ncg = (d.nxs + W - 1) / W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int cg = blk % ncg, r0 = (blk / ncg) * FS_S;
+    const int nr = min(FS_S, d.ny - r0);
+    const int L = threadIdx.x;
+    const int cx = cg * W + L - RF;
+    int gx = cx % d.nxs;
+    gx += gx < 0 ? d.nxs : 0;
+    const bool put = L >= RF && L < 64 - RF && cx < d.nxs;
+    const bool gp = d.window && window_col(gx, glob(d.st)->origin, d.nxs) >= d.nx;
+    const R N = (R)d.npass;
+    auto at = [&](int j) {
+        int gy = j % d.ny;
+        gy += gy < 0 ? d.ny : 0;
+        return (size_t)gx + (size_t)gy * d.nxs;
+    };
+    const gptr<const R> in[3] = {glob(i0), glob(i1), glob(i2)};
+    R a[NRW][3];
+#pragma unroll
+    for (int q = 0; q < NRW; ++q) {
+        const size_t g = at(r0 - RF + q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[q][c] = in[c][g];
+    }
+#pragma unroll
+    for (int pass = 0; pass < RF; ++pass) {
+        const bool comp = pass == d.npass;
+        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+#pragma unroll
+        for (int q = 0; q < NRW; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R l = __shfl_up(a[q][c], 1), r = __shfl_down(a[q][c], 1);
+                a[q][c] = gp ? R(0) : w0 * l + w1 * a[q][c] + w0 * r;
+            }
+        }
+    }
+#pragma unroll
+    for (int pass = 0; pass < RF; ++pass) {
+        const bool comp = pass == d.npass;
+        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+        R b[NRW][3];
+#pragma unroll
+        for (int q = 1; q < NRW - 1; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) b[q][c] = w0 * a[q - 1][c] + w1 * a[q][c] + w0 * a[q + 1][c];
+        }
+#pragma unroll
+        for (int q = 1; q < NRW - 1; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[q][c] = b[q][c];
+        }
+    }
+    R *const out[3] = {o0, o1, o2};
+#pragma unroll
+    for (int m = 0; m < FS_S; ++m) {
+        if (put && m < nr) {
+            const size_t g = at(r0 + m);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) glob(out[c])[g] = a[RF + m][c];
+        }
+    }
+}
+
 // Row a7 in streaming form, for one simulation: each wavefront advances a
 // strip of YS_S rows and YS_W columns.  Lane L holds column c0 + L - 1 of
 // every row, so one row of a plane is a single contiguous load of the
@@ -763,6 +851,9 @@ constexpr int YS_S = 8;
 template <typename R>
 __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
 {
+    // no contraction into fma: the tile and streaming forms (and the batched
+    // launches) must round every term alike
+#pragma clang fp contract(off)
     const int ncg = (d.nxs + YS_W - 1) / YS_W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int cg = blk % ncg, r0 = (blk / ncg) * YS_S;
@@ -1458,6 +1549,22 @@ template <typename R>
 hipError_t Launch<R>::filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
                              const R *i2, R *o0, R *o1, R *o2, hipStream_t s)
 {
+    const int rf = d.npass + (d.compensate ? 1 : 0);
+    if (nplanes == 3 && rf >= 1 && rf <= MAX_FR) {
+        const int nst = (d.ny + FS_S - 1) / FS_S;
+        auto go = [&](auto kern, int w) {
+            hipLaunchKernelGGL(kern, dim3(((d.nxs + w - 1) / w) * nst), dim3(64), 0, s, d, i0, i1,
+                               i2, o0, o1, o2);
+        };
+        static_assert(MAX_FR == 4, "one instance per filter halo");
+        switch (rf) {
+        case 1: go(k_filter_s<R, 1>, 62); break;
+        case 2: go(k_filter_s<R, 2>, 60); break;
+        case 3: go(k_filter_s<R, 3>, 58); break;
+        default: go(k_filter_s<R, 4>, 56); break;
+        }
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_filter<R>, dim3(d.ntiles), dim3(NT), 0, s, d, nplanes, i0, i1, i2, o0,
                        o1, o2);
     return hipGetLastError();

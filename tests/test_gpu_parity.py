@@ -95,6 +95,9 @@ CASES = {
     "no_filter_direct": (two_species(34, 18, 3.4, 1.8, filter_passes=0), False, True),
     "three_passes": (two_species(48, 32, 4.8, 3.2, filter_passes=3, filter_compensate=True),
                      False, False),
+    # three strips of columns (the last one ragged) and five of rows; halo 3
+    "two_passes_comp_130x40": (two_species(130, 40, 13.0, 4.0, filter_passes=2,
+                                           filter_compensate=True), False, False),
     "single_tile_4x4": (two_species(4, 4, 0.4, 0.4, filter_passes=1), False, False),
     "single_tile_2x2": (two_species(2, 2, 0.2, 0.2, filter_passes=2), False, True),
     "two_tiles_wrap_18x20": (two_species(18, 20, 1.8, 2.0, filter_passes=1), False, False),
