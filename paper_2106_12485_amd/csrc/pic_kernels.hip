@@ -755,6 +755,108 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
     }
 }
 
+// Row a5 in streaming form, for the three current planes of one simulation:
+// each wavefront folds one tile row of four horizontally adjacent tiles, lane
+// L holding column L % 16 of tile 4 c + L / 16 on every row of the tile.
+// Each cell adds, in ascending (oy, ox) order, the entries of the tile images
+// whose block covers it, as fold_body does, so the sums agree bit for bit.
+// For a full-height tile at least 3 columns wide a lane reads at most one
+// image beyond its own in each direction (the left one for lx < 2, the right
+// one for lx = w - 1; the lower one for rows 0 and 1, the upper one for row
+// 15): all of the tile row's loads go out first, unconditionally (a lane
+// that needs no neighbour reads its own entry again and adds zero), then the
+// sums.  Other tiles take the general per-cell path.
+template <typename R>
+__global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
+{
+    const int ngx = (d.ntx + 3) / 4;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int ty = blk / ngx, tx = (blk % ngx) * 4 + (int)(threadIdx.x >> 4);
+    const int lx = threadIdx.x & 15;
+    if (tx >= d.ntx) return;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    if (lx >= w) return;
+    const bool gap = d.window && window_col(x0 + lx, glob(d.st)->origin, d.nxs) >= d.nx;
+    R *const out[3] = {o0, o1, o2};
+    auto img = [&](int a, int b) {
+        return glob<const R>(d.blk + (size_t)(a + b * d.ntx) * 3 * BP);
+    };
+    if (h == TY && w >= 3) {
+        const int txl = wrapi(tx - 1, d.ntx), txr = wrapi(tx + 1, d.ntx);
+        const int tyl = wrapi(ty - 1, d.nty), tyu = wrapi(ty + 1, d.nty);
+        const int wl = min(TX, d.nxs - txl * TX), hl = min(TY, d.ny - tyl * TY);
+        const int xo = lx < 2 ? -1 : (lx == w - 1 ? 1 : 0);
+        const int txn = xo < 0 ? txl : (xo > 0 ? txr : tx);
+        // column (px + 1) of the cell in its own image and in the x neighbour's
+        const int cxo = lx + 1, cxn = xo < 0 ? lx + wl + 1 : (xo > 0 ? 0 : lx + 1);
+        const gptr<const R> io = img(tx, ty), ixn = img(txn, ty);
+        const gptr<const R> il = img(tx, tyl), ilx = img(txn, tyl);
+        const gptr<const R> iu = img(tx, tyu), iux = img(txn, tyu);
+        R own[TY][3], xn[TY][3], lo[2][3], lox[2][3], up[3], upx[3];
+#pragma unroll
+        for (int ly = 0; ly < TY; ++ly) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                own[ly][c] = io[c * BP + cxo + (ly + 1) * PX];
+                xn[ly][c] = ixn[c * BP + cxn + (ly + 1) * PX];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lo[r][c] = il[c * BP + cxo + (r + hl + 1) * PX];
+                lox[r][c] = ilx[c * BP + cxn + (r + hl + 1) * PX];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            up[c] = iu[c * BP + cxo];
+            upx[c] = iux[c * BP + cxn];
+        }
+        // one level of images: the x neighbour first when it lies to the left
+        auto level = [&](R &a, R o, R n) {
+            a += xo < 0 ? n : o;
+            a += xo < 0 ? o : (xo > 0 ? n : R(0));
+        };
+#pragma unroll
+        for (int ly = 0; ly < TY; ++ly) {
+            const size_t g = (size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                R a = 0;
+                if (ly < 2) level(a, lo[ly][c], lox[ly][c]);
+                level(a, own[ly][c], xn[ly][c]);
+                if (ly == TY - 1) level(a, up[c], upx[c]);
+                glob(out[c])[g] = gap ? R(0) : a;
+            }
+        }
+        return;
+    }
+    for (int ly = 0; ly < h; ++ly) {
+        R a[3] = {0, 0, 0};
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int tyn = wrapi(ty + oy, d.nty);
+            const int hn = min(TY, d.ny - tyn * TY);
+            const int py = oy == 0 ? ly : (oy < 0 ? ly + hn : ly - h);
+            if (py < -1 || py >= hn + 2) continue;
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int txn = wrapi(tx + ox, d.ntx);
+                const int wn = min(TX, d.nxs - txn * TX);
+                const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
+                if (px < -1 || px >= wn + 2) continue;
+                const gptr<const R> b = img(txn, tyn);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a[c] += b[c * BP + (px + 1) + (py + 1) * PX];
+            }
+        }
+        const size_t g = (size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) glob(out[c])[g] = gap ? R(0) : a[c];
+    }
+}
+
 // Row a6 in streaming form, for the three current planes of one simulation:
 // each wavefront filters a strip of FS_S rows and 64 - 2 RF columns, where
 // RF = npass + compensate.  Lane L holds column c0 + L - RF of every row.
@@ -1541,6 +1643,11 @@ hipError_t Launch<R>::settle(const SimDev<R> &d, hipStream_t s, bool only_if_shi
 template <typename R>
 hipError_t Launch<R>::fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s)
 {
+    if (nplanes == 3) {
+        hipLaunchKernelGGL(k_fold_s<R>, dim3(((d.ntx + 3) / 4) * d.nty), dim3(64), 0, s, d, o0,
+                           o1, o2);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_fold<R>, dim3(d.ntiles), dim3(NT), 0, s, d, nplanes, o0, o1, o2);
     return hipGetLastError();
 }
