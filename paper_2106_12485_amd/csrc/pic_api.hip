@@ -101,9 +101,11 @@ int layout(const pic_cfg *c, Layout *L)
         L->cap[s] = (int)cap;
         maxcap = std::max(maxcap, (int)cap);
     }
-    // outbox: 1/16 of the slots per tile (a leaver fraction far above what a
-    // particle moving at most one cell per step through a 16-cell tile gives)
-    L->cap_out = std::min(MAX_OUT, std::max(64, (maxcap / 16 + 63) / 64 * 64));
+    // outbox: a quarter of the slots per tile.  A particle crosses at most one
+    // cell per step, so only those in the tile's outer ring of cells (60 of
+    // 256) can leave: a uniformly filled tile at capacity sends at most 23% of
+    // its slots, even when every one of them moves outwards at close to c.
+    L->cap_out = std::max(64, (maxcap / 4 + 63) / 64 * 64);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;

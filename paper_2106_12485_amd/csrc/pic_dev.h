@@ -29,7 +29,6 @@ constexpr int NT = 256;             // threads per block (4 wavefronts)
 constexpr int NTP = 512;            // threads per push block (8 wavefronts)
 constexpr int NTB = 512;            // threads per batched push block
 constexpr int MAX_SP = 4;
-constexpr int MAX_OUT = 2048;       // outbox slots per tile and species
 constexpr int MAX_FR = 4;           // largest filter halo (passes + compensator)
 constexpr int QX = TX + 2 * MAX_FR; // LDS pitch of the filter block
 constexpr int QY = TY + 2 * MAX_FR;

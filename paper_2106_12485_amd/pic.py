@@ -155,7 +155,8 @@ DEPOSIT_MODES = {"reduction": 0, "commutative": 1}
 def make_cfg(w, fp64=False, load=True, capacity_factor=0.0, deposit="reduction") -> Cfg:
     """Fill the C configuration from a workload description (any object with
     nx, ny, lx, ly, dt, species, moving_window, filter_passes,
-    filter_compensate, laser, seed attributes)."""
+    filter_compensate, laser, seed and optionally capacity_factor
+    attributes)."""
     c = Cfg()
     c.nx, c.ny = int(w.nx), int(w.ny)
     c.lx, c.ly, c.dt = float(w.lx), float(w.ly), float(w.dt)
@@ -185,7 +186,8 @@ def make_cfg(w, fp64=False, load=True, capacity_factor=0.0, deposit="reduction")
     c.fp64 = int(bool(fp64))
     c.seed = int(getattr(w, "seed", 0)) & 0xFFFFFFFFFFFFFFFF
     c.load = int(bool(load))
-    c.capacity_factor = float(capacity_factor)
+    # an explicit factor wins over the workload's own
+    c.capacity_factor = float(capacity_factor or getattr(w, "capacity_factor", 0.0))
     c.deposit_mode = DEPOSIT_MODES[deposit]
     return c
 
