@@ -220,9 +220,12 @@ int pic_set_fields(pic_sim *sim, const double *f6, void *stream);
 int pic_get_fields(pic_sim *sim, double *f6, void *stream);
 
 /* Current of the last step (3 * nx * ny doubles): filtered != 0 returns the
- * current the field solver used, 0 the folded current before filtering.  With
- * the moving window it is given in the window of the step that deposited it
- * (before that step's shift, if any).  Synchronises. */
+ * current the field solver used, 0 the folded current before filtering.  A
+ * single simulation's step filters inside its field-solver launch, so a
+ * filtered request runs the filter on the stored folded current first (same
+ * arithmetic, same result).  With the moving window the current is given in
+ * the window of the step that deposited it (before that step's shift, if
+ * any).  Synchronises. */
 int pic_get_current(pic_sim *sim, int filtered, double *j3, void *stream);
 
 /* Set the step counter and the number of window shifts done (to continue a
@@ -234,8 +237,10 @@ int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream);
  * not from the graph).  pic_timing(sim, 1) resets and starts, 0 stops.
  * pic_timing_read fills ms[k] (summed milliseconds) and launches[k] for
  * k < nk of: 0 push + deposit (its last block flips the particle buffers),
- * 1 hand-off of pending leavers (settle), 2 fold, 3 filter, 4 Yee and the
- * step end (field buffer flip, step count), 5 moving-window shift.
+ * 1 hand-off of pending leavers (settle), 2 fold, 3 filter (only the
+ * requests of pic_get_current: the step filters inside the Yee launch),
+ * 4 current filter + Yee and the step end (field buffer flip, step count),
+ * 5 moving-window shift.
  * Synchronises. */
 #define PIC_NK 6
 int pic_timing(pic_sim *sim, int enable, void *stream);

@@ -374,12 +374,7 @@ int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
         rc = timed(s, 2, st, [&] { return Launch<R>::fold(d, 3, d.J[0], d.J[1], d.J[2], st); });
         if (rc) return rc;
     }
-    if (d.npass > 0) {
-        rc = timed(s, 3, st, [&] {
-            return Launch<R>::filter(d, 3, d.J[0], d.J[1], d.J[2], d.Jf[0], d.Jf[1], d.Jf[2], st);
-        });
-        if (rc) return rc;
-    }
+    // the Yee launch filters J itself (Jf is only written on request)
     rc = timed(s, 4, st, [&] { return Launch<R>::yee(d, st); });
     if (rc) return rc;
     if (d.window) {
@@ -682,6 +677,21 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
     return PIC_OK;
 }
 
+// The step filters the current inside the Yee launch, so a request for the
+// filtered current filters the last step's J into Jf first (same arithmetic).
+template <typename R>
+int get_current(pic_sim *sim, const SimDev<R> &d, int filtered, double *j3, hipStream_t st)
+{
+    if (filtered && d.npass > 0) {
+        const int rc = timed(sim, 3, st, [&] {
+            return Launch<R>::filter(d, 3, d.J[0], d.J[1], d.J[2], d.Jf[0], d.Jf[1], d.Jf[2], st,
+                                     true);
+        });
+        if (rc) return rc;
+    }
+    return do_planes(sim, filtered ? d.Jf : d.J, 3, j3, false, st, 1);
+}
+
 }  // namespace
 
 #define DISPATCH(sim, call_f, call_d) ((sim)->cfg.fp64 ? (call_d) : (call_f))
@@ -852,8 +862,8 @@ int pic_get_current(pic_sim *sim, int filtered, double *j3, void *stream)
 {
     if (!sim || !j3) return fail(PIC_E_ARG, "bad sim or NULL planes");
     hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim, do_planes(sim, filtered ? sim->df.Jf : sim->df.J, 3, j3, false, st, 1),
-                    do_planes(sim, filtered ? sim->dd.Jf : sim->dd.J, 3, j3, false, st, 1));
+    return DISPATCH(sim, get_current(sim, sim->df, filtered, j3, st),
+                    get_current(sim, sim->dd, filtered, j3, st));
 }
 
 int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream)

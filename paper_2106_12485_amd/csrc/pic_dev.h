@@ -223,8 +223,11 @@ template <typename R> struct Launch {
     // only_if_shift: skip unless the last step shifted the moving window
     static hipError_t settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift = false);
     static hipError_t fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s);
+    // before_shift (three planes only): keep the window gap of the last
+    // step's deposit although that step's end has shifted the window
     static hipError_t filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
-                             const R *i2, R *o0, R *o1, R *o2, hipStream_t s);
+                             const R *i2, R *o0, R *o1, R *o2, hipStream_t s,
+                             bool before_shift = false);
     static hipError_t yee(const SimDev<R> &d, hipStream_t s);
     static hipError_t window(const SimDev<R> &d, hipStream_t s);
     static hipError_t load(const SimDev<R> &d, int sp, hipStream_t s);

@@ -857,23 +857,62 @@ __global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
     }
 }
 
-// Row a6 in streaming form, for the three current planes of one simulation:
-// each wavefront filters a strip of FS_S rows and 64 - 2 RF columns, where
-// RF = npass + compensate.  Lane L holds column c0 + L - RF of every row.
-// The x passes take their neighbours from the adjacent lanes, the y passes
-// from the rows held in registers.  The outermost lanes and rows take
-// arbitrary values that move one cell inwards per pass, so after RF passes
-// lanes [RF, 64 - RF) and rows [RF, FS_S + RF) are exact.  Same arithmetic
-// as filter_body, term for term.
+// Row a6 in streaming form, for the three current planes of one simulation
+// (the step runs the filter inside k_yee_s; this kernel serves requests for
+// the filtered current): each wavefront filters a strip of FS_S rows and
+// 64 - 2 RF columns, where RF = npass + compensate.  Lane L holds column
+// c0 + L - RF of every row.  The x passes take their neighbours from the
+// adjacent lanes, the y passes from the rows held in registers.  The
+// outermost lanes and rows take arbitrary values that move one cell inwards
+// per pass, so after RF passes lanes [RF, 64 - RF) and rows [RF, FS_S + RF)
+// are exact.  Same arithmetic as filter_body, term for term.
 constexpr int FS_S = 8;
+
+// The N + c passes of the filter on rows held in registers, one column per
+// lane: x passes with the adjacent lanes' values (gap columns held at zero),
+// then y passes along the rows.  Lanes and rows within RF of the edges end
+// with arbitrary values.
+template <typename R, int RF, int NR>
+__device__ __forceinline__ void filter_rows(R (&a)[NR][3], bool gp, int npass)
+{
+#pragma clang fp contract(off)
+    const R N = (R)npass;
+#pragma unroll
+    for (int pass = 0; pass < RF; ++pass) {
+        const bool comp = pass == npass;
+        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R l = __shfl_up(a[q][c], 1), r = __shfl_down(a[q][c], 1);
+                a[q][c] = gp ? R(0) : w0 * l + w1 * a[q][c] + w0 * r;
+            }
+        }
+    }
+#pragma unroll
+    for (int pass = 0; pass < RF; ++pass) {
+        const bool comp = pass == npass;
+        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
+        R b[NR][3];
+#pragma unroll
+        for (int q = 1; q < NR - 1; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) b[q][c] = w0 * a[q - 1][c] + w1 * a[q][c] + w0 * a[q + 1][c];
+        }
+#pragma unroll
+        for (int q = 1; q < NR - 1; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[q][c] = b[q][c];
+        }
+    }
+}
 
 template <typename R, int RF>
 __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const R *i1,
-                                                const R *i2, R *o0, R *o1, R *o2)
+                                                const R *i2, R *o0, R *o1, R *o2,
+                                                int before_shift)
 {
-    // no contraction into fma: the tile and streaming forms (and the batched
-    // launches) must round every term alike
-#pragma clang fp contract(off)
     constexpr int W = 64 - 2 * RF, NRW = FS_S + 2 * RF;
     const int ncg = (d.nxs + W - 1) / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -884,8 +923,9 @@ __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const
     int gx = cx % d.nxs;
     gx += gx < 0 ? d.nxs : 0;
     const bool put = L >= RF && L < 64 - RF && cx < d.nxs;
-    const bool gp = d.window && window_col(gx, glob(d.st)->origin, d.nxs) >= d.nx;
-    const R N = (R)d.npass;
+    // before_shift: the gap of the window the last step deposited in
+    const int origin = wrapi(glob(d.st)->origin - (before_shift ? glob(d.st)->shift : 0), d.nxs);
+    const bool gp = d.window && window_col(gx, origin, d.nxs) >= d.nx;
     auto at = [&](int j) {
         int gy = j % d.ny;
         gy += gy < 0 ? d.ny : 0;
@@ -899,35 +939,7 @@ __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const
 #pragma unroll
         for (int c = 0; c < 3; ++c) a[q][c] = in[c][g];
     }
-#pragma unroll
-    for (int pass = 0; pass < RF; ++pass) {
-        const bool comp = pass == d.npass;
-        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
-#pragma unroll
-        for (int q = 0; q < NRW; ++q) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const R l = __shfl_up(a[q][c], 1), r = __shfl_down(a[q][c], 1);
-                a[q][c] = gp ? R(0) : w0 * l + w1 * a[q][c] + w0 * r;
-            }
-        }
-    }
-#pragma unroll
-    for (int pass = 0; pass < RF; ++pass) {
-        const bool comp = pass == d.npass;
-        const R w0 = comp ? -N / R(4) : R(0.25), w1 = comp ? (R(4) + R(2) * N) / R(4) : R(0.5);
-        R b[NRW][3];
-#pragma unroll
-        for (int q = 1; q < NRW - 1; ++q) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) b[q][c] = w0 * a[q - 1][c] + w1 * a[q][c] + w0 * a[q + 1][c];
-        }
-#pragma unroll
-        for (int q = 1; q < NRW - 1; ++q) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a[q][c] = b[q][c];
-        }
-    }
+    filter_rows<R, RF>(a, gp, d.npass);
     R *const out[3] = {o0, o1, o2};
 #pragma unroll
     for (int m = 0; m < FS_S; ++m) {
@@ -939,32 +951,38 @@ __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const
     }
 }
 
-// Row a7 in streaming form, for one simulation: each wavefront advances a
-// strip of YS_S rows and YS_W columns.  Lane L holds column c0 + L - 1 of
-// every row, so one row of a plane is a single contiguous load of the
-// wavefront; x neighbours come from the adjacent lanes and y neighbours from
-// the rows held in registers.  All loads of the strip go out before the
-// first update.  Lane 0 (B half at i - 1) and lanes YS_W + 1, YS_W + 2 (E at
-// i + 1, i + 2) are the halo: lanes 1..YS_W end with complete results.  The
-// arithmetic is that of yee_body, term for term.
-constexpr int YS_W = 61;
+// Rows a6 + a7 in streaming form, for one simulation: each wavefront filters
+// the current and advances the fields on a strip of YS_S rows.  Lane L holds
+// column c0 + L - P of every row, P = max(1, RF), so one row of a plane is a
+// single contiguous load of the wavefront; x neighbours come from the
+// adjacent lanes and y neighbours from the rows held in registers.  All loads
+// of the strip go out before the first update.  With RF = npass + compensate
+// > 0 the current is J filtered in registers (filter_rows, exact on lanes
+// RF .. 63 - RF); with RF = 0 it is read as is.  The Yee halo is lane P - 1
+// (B half at i - 1) and lanes beyond the strip (E at i + 1, i + 2): lanes
+// P .. 62 - P end with complete results.  The arithmetic is that of
+// filter_body and yee_body, term for term.
 constexpr int YS_S = 8;
 
-template <typename R>
+// Output columns of one wavefront of k_yee_s<R, RF>.
+__host__ __device__ constexpr int yee_strip_w(int rf) { return 63 - 2 * (rf > 1 ? rf : 1); }
+
+template <typename R, int RF>
 __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
 {
     // no contraction into fma: the tile and streaming forms (and the batched
     // launches) must round every term alike
 #pragma clang fp contract(off)
-    const int ncg = (d.nxs + YS_W - 1) / YS_W;
+    constexpr int P = RF > 1 ? RF : 1, W = yee_strip_w(RF);
+    const int ncg = (d.nxs + W - 1) / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int cg = blk % ncg, r0 = (blk / ncg) * YS_S;
     const int nr = min(YS_S, d.ny - r0);
     const int L = threadIdx.x;
-    const int cx = cg * YS_W + L - 1;
+    const int cx = cg * W + L - P;
     int gx = cx % d.nxs;
     gx += gx < 0 ? d.nxs : 0;
-    const bool put = L >= 1 && L <= YS_W && cx < d.nxs;
+    const bool put = L >= P && L < P + W && cx < d.nxs;
     const int par = glob(d.st)->parity, origin = glob(d.st)->origin;
     const bool gp = d.window && window_col(gx, origin, d.nxs) >= d.nx;
     const R hdt = R(0.5) * d.dt;
@@ -973,8 +991,11 @@ __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
         gy += gy < 0 ? d.ny : 0;
         return (size_t)gx + (size_t)gy * d.nxs;
     };
-    // rows r0 - 1 + q: E for q in [0, YS_S + 3), B in [0, YS_S + 2), J in [1, YS_S + 2)
-    R eo[YS_S + 3][3], bo[YS_S + 2][3], jj[YS_S + 1][3];
+    // rows r0 - 1 + q: E for q in [0, YS_S + 3), B in [0, YS_S + 2); the
+    // current on rows r0 .. r0 + YS_S, filtered here from J (RF > 0: rows
+    // r0 - RF .. r0 + YS_S + RF of J) or read as is
+    constexpr int NJ = YS_S + 1 + 2 * RF;
+    R eo[YS_S + 3][3], bo[YS_S + 2][3], ja[NJ][3];
 #pragma unroll
     for (int q = 0; q < YS_S + 3; ++q) {
         const size_t g = at(r0 - 1 + q);
@@ -982,9 +1003,16 @@ __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
         for (int c = 0; c < 3; ++c) {
             eo[q][c] = glob<const R>(par ? d.F[1][c] : d.F[0][c])[g];
             if (q < YS_S + 2) bo[q][c] = glob<const R>(par ? d.F[1][3 + c] : d.F[0][3 + c])[g];
-            if (q >= 1 && q < YS_S + 2) jj[q - 1][c] = glob<const R>(d.Jf[c])[g];
         }
     }
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const size_t g = at(r0 - RF + q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ja[q][c] = glob<const R>(RF > 0 ? d.J[c] : d.Jf[c])[g];
+    }
+    if constexpr (RF > 0) filter_rows<R, RF>(ja, gp, d.npass);
+    R (&jj)[NJ][3] = ja;  // jj[RF + m]: row r0 + m
     // B half step, rows r0 - 1 .. r0 + YS_S
     R bh[YS_S + 2][3];
 #pragma unroll
@@ -1007,9 +1035,9 @@ __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
         const R dBz_dx = (bh[q][2] - bz0) * d.idx;
         const R dBy_dx = (bh[q][1] - by0) * d.idx;
         const R dBx_dy = (bh[q][0] - bh[q - 1][0]) * d.idy;
-        en[q - 1][0] = gp ? R(0) : eo[q][0] + d.dt * (dBz_dy - jj[q - 1][0]);
-        en[q - 1][1] = gp ? R(0) : eo[q][1] + d.dt * (-dBz_dx - jj[q - 1][1]);
-        en[q - 1][2] = gp ? R(0) : eo[q][2] + d.dt * (dBy_dx - dBx_dy - jj[q - 1][2]);
+        en[q - 1][0] = gp ? R(0) : eo[q][0] + d.dt * (dBz_dy - jj[RF + q - 1][0]);
+        en[q - 1][1] = gp ? R(0) : eo[q][1] + d.dt * (-dBz_dx - jj[RF + q - 1][1]);
+        en[q - 1][2] = gp ? R(0) : eo[q][2] + d.dt * (dBy_dx - dBx_dy - jj[RF + q - 1][2]);
     }
     // B half step on the strip's rows, and write out
     const int npar = par ^ 1;
@@ -1654,14 +1682,14 @@ hipError_t Launch<R>::fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2,
 
 template <typename R>
 hipError_t Launch<R>::filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
-                             const R *i2, R *o0, R *o1, R *o2, hipStream_t s)
+                             const R *i2, R *o0, R *o1, R *o2, hipStream_t s, bool before_shift)
 {
     const int rf = d.npass + (d.compensate ? 1 : 0);
     if (nplanes == 3 && rf >= 1 && rf <= MAX_FR) {
         const int nst = (d.ny + FS_S - 1) / FS_S;
         auto go = [&](auto kern, int w) {
             hipLaunchKernelGGL(kern, dim3(((d.nxs + w - 1) / w) * nst), dim3(64), 0, s, d, i0, i1,
-                               i2, o0, o1, o2);
+                               i2, o0, o1, o2, (int)before_shift);
         };
         static_assert(MAX_FR == 4, "one instance per filter halo");
         switch (rf) {
@@ -1680,8 +1708,19 @@ hipError_t Launch<R>::filter(const SimDev<R> &d, int nplanes, const R *i0, const
 template <typename R>
 hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
 {
-    const int nstrip = ((d.nxs + YS_W - 1) / YS_W) * ((d.ny + YS_S - 1) / YS_S);
-    hipLaunchKernelGGL(k_yee_s<R>, dim3(nstrip), dim3(64), 0, s, d);
+    const int rf = d.npass > 0 ? d.npass + (d.compensate ? 1 : 0) : 0;
+    const int nsy = (d.ny + YS_S - 1) / YS_S;
+    auto go = [&](auto kern, int w) {
+        hipLaunchKernelGGL(kern, dim3(((d.nxs + w - 1) / w) * nsy), dim3(64), 0, s, d);
+    };
+    static_assert(MAX_FR == 4, "one instance per filter halo");
+    switch (rf) {
+    case 0: go(k_yee_s<R, 0>, yee_strip_w(0)); break;
+    case 1: go(k_yee_s<R, 1>, yee_strip_w(1)); break;
+    case 2: go(k_yee_s<R, 2>, yee_strip_w(2)); break;
+    case 3: go(k_yee_s<R, 3>, yee_strip_w(3)); break;
+    default: go(k_yee_s<R, 4>, yee_strip_w(4)); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_step_end<R>, dim3(1), dim3(64), 0, s, d);
