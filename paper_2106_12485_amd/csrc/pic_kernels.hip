@@ -302,11 +302,13 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
                 dir = dir_index(dtx, dty);
             }
             // stayers: one contiguous run per wavefront in buffer ppar ^ 1
+            // (every lane of the wavefront runs this part: lane 0 is active
+            // and readfirstlane gives its value to the others)
             const unsigned long long ms = __ballot(stay);
             if (ms) {
                 int off = 0;
                 if (lane == 0) off = atomicAdd(&s_out, (int)__popcll(ms));
-                off = __shfl(off, 0);
+                off = __builtin_amdgcn_readfirstlane(off);
                 if (stay) {
                     const unsigned q = (unsigned)(off + (int)__popcll(ms & below));
                     if (q < (unsigned)P.cap) {
@@ -328,7 +330,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
             if (ml) {
                 int off = 0;
                 if (lane == 0) off = atomicAdd(&s_nob, (int)__popcll(ml));
-                off = __shfl(off, 0);
+                off = __builtin_amdgcn_readfirstlane(off);
                 if (send) {
                     const int slot = off + (int)__popcll(ml & below);
                     if (slot < d.cap_out) {
