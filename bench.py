@@ -44,7 +44,8 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_push_deposit_clouds_1024x102
 def measured_traffic():
     """HBM bytes per k_push_deposit launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (calibrated on a plain copy), or None if
-    that summary was taken on other kernel sources than the current ones."""
+    that summary was taken on other kernel sources or build flags than the
+    current ones."""
     import hashlib
     try:
         vals = {}
@@ -52,10 +53,14 @@ def measured_traffic():
             parts = line.split()
             if len(parts) == 2 and parts[0].endswith(("sha256", "per_launch")):
                 vals[parts[0]] = parts[1]
-        src = os.path.join(ROOT, "paper_2106_12485_amd", "csrc")
+        pkg = os.path.join(ROOT, "paper_2106_12485_amd")
+        src = os.path.join(pkg, "csrc")
         kh = hashlib.sha256(open(os.path.join(src, "pic_kernels.hip"), "rb").read()).hexdigest()
         hh = hashlib.sha256(open(os.path.join(src, "pic_dev.h"), "rb").read()).hexdigest()
-        if vals.get("kernel_source_sha256") != kh or vals.get("header_source_sha256") != hh:
+        # the compiler flags live in build.py
+        bh = hashlib.sha256(open(os.path.join(pkg, "build.py"), "rb").read()).hexdigest()
+        if (vals.get("kernel_source_sha256") != kh or vals.get("header_source_sha256") != hh
+                or vals.get("build_source_sha256") != bh):
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
