@@ -26,7 +26,7 @@
  * The grid loops (filter, Yee, window shift) are split over rows, which
  * changes no result.
  *
- * Where the paper is silent the readings are (each is restated in the design doc):
+ * Where the paper is silent the readings are:
  *   - normalised units: c = 1, time in 1/w_p, length in c/w_p, u = gamma v,
  *     fields in m c w_p / e, dE/dt = curl B - J, dB/dt = -curl E, div E = rho;
  *   - standard 2D Yee staggering: Ex(i+1/2,j) Ey(i,j+1/2) Ez(i,j)
