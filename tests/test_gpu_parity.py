@@ -204,6 +204,45 @@ def test_graph_replay_equals_direct_launches():
             assert np.array_equal(pa[c][oa], pb[c][ob]), c
 
 
+@pytest.mark.parametrize("window", [False, True])
+def test_filtered_current_requests_change_nothing(window):
+    """The step filters J inside its field-solver launch; a request for the
+    filtered current filters the stored J on its own.  Requests between the
+    steps must leave the run bit for bit as it was, and each must return the
+    current that step's solver used: the one of a run that filters in a
+    launch of its own (the batched path) over the same steps."""
+    if window:
+        w = two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True, filter_passes=1,
+                        filter_compensate=True)
+    else:
+        w = two_species(40, 36, 4.0, 3.6, filter_passes=2, filter_compensate=True)
+    rng = np.random.default_rng(31)
+    parts, f = random_state(w, rng)
+    a, _ = setup_pair(w, parts, f)
+    b, _ = setup_pair(w, parts, f)
+    jf = []
+    for _ in range(12):
+        a.step(1)
+        jf.append(a.get_current(True))
+        jf.append(a.get_current(True))
+    b.step(12)
+    assert np.array_equal(a.get_fields(), b.get_fields())
+    assert np.array_equal(a.get_current(False), b.get_current(False))
+    assert np.array_equal(jf[-1], b.get_current(True))
+    for x, y in zip(jf[0::2], jf[1::2]):
+        assert np.array_equal(x, y)
+    if not window:
+        # a batch of one filters in the tile-form launch of its own
+        from paper_2106_12485_amd import Batch
+        c, _ = setup_pair(w, parts, f)
+        bt = Batch(1, c.layout()["ntx"] * c.layout()["nty"])
+        for n in range(12):
+            bt.step([c], 1)
+            assert np.array_equal(c.get_current(True), jf[2 * n]), n
+        assert np.array_equal(c.get_fields(), b.get_fields())
+        bt.close()
+
+
 def test_set_get_roundtrip_is_exact():
     w = two_species(40, 36, 4.0, 3.6)
     rng = np.random.default_rng(13)
