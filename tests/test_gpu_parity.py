@@ -98,6 +98,14 @@ CASES = {
     # three strips of columns (the last one ragged) and five of rows; halo 3
     "two_passes_comp_130x40": (two_species(130, 40, 13.0, 4.0, filter_passes=2,
                                            filter_compensate=True), False, False),
+    # odd sizes against the streaming strips (61/59/57/55 columns by 8 rows for
+    # filter + Yee, 4-tile rows for the fold): ragged strips on both axes
+    "odd_67x9": (two_species(67, 9, 6.7, 0.9, filter_passes=1), False, False),
+    "odd_66x66_three": (two_species(66, 66, 6.6, 6.6, filter_passes=3), False, False),
+    "odd_62x31_four": (two_species(62, 31, 6.2, 3.1, filter_passes=4), False, False),
+    "narrow_3x70": (two_species(3, 70, 0.3, 7.0, filter_passes=1), False, False),
+    "window_121x23": (two_species(121, 23, 2.42, 4.6, dt=0.014, moving_window=True,
+                                  filter_passes=2, filter_compensate=True), False, False),
     "single_tile_4x4": (two_species(4, 4, 0.4, 0.4, filter_passes=1), False, False),
     "single_tile_2x2": (two_species(2, 2, 0.2, 0.2, filter_passes=2), False, True),
     "two_tiles_wrap_18x20": (two_species(18, 20, 1.8, 2.0, filter_passes=1), False, False),
