@@ -758,27 +758,32 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
 }
 
 // Row a5 in streaming form, for the three current planes of one simulation:
-// each wavefront folds one tile row of four horizontally adjacent tiles, lane
-// L holding column L % 16 of tile 4 c + L / 16 on every row of the tile.
+// each wavefront folds half (FH rows) of a tile row of four horizontally
+// adjacent tiles, lane L holding column L % 16 of tile 4 c + L / 16.
 // Each cell adds, in ascending (oy, ox) order, the entries of the tile images
 // whose block covers it, as fold_body does, so the sums agree bit for bit.
 // For a full-height tile at least 3 columns wide a lane reads at most one
 // image beyond its own in each direction (the left one for lx < 2, the right
 // one for lx = w - 1; the lower one for rows 0 and 1, the upper one for row
-// 15): all of the tile row's loads go out first, unconditionally (a lane
+// 15): all of the wavefront's loads go out first, unconditionally (a lane
 // that needs no neighbour reads its own entry again and adds zero), then the
 // sums.  Other tiles take the general per-cell path.
+constexpr int FH = TY / 2;  // rows of a tile row per wavefront of k_fold_s
+
 template <typename R>
 __global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
 {
     const int ngx = (d.ntx + 3) / 4;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int ty = blk / ngx, tx = (blk % ngx) * 4 + (int)(threadIdx.x >> 4);
+    // rows FH * half .. of tile row ty
+    const int rg = blk / ngx, ty = rg >> 1, half = rg & 1;
+    const int tx = (blk % ngx) * 4 + (int)(threadIdx.x >> 4);
     const int lx = threadIdx.x & 15;
     if (tx >= d.ntx) return;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
-    if (lx >= w) return;
+    const int ly0 = half * FH, ly1 = min(h, ly0 + FH);
+    if (lx >= w || ly0 >= ly1) return;
     const bool gap = d.window && window_col(x0 + lx, glob(d.st)->origin, d.nxs) >= d.nx;
     R *const out[3] = {o0, o1, o2};
     auto img = [&](int a, int b) {
@@ -795,27 +800,28 @@ __global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
         const gptr<const R> io = img(tx, ty), ixn = img(txn, ty);
         const gptr<const R> il = img(tx, tyl), ilx = img(txn, tyl);
         const gptr<const R> iu = img(tx, tyu), iux = img(txn, tyu);
-        R own[TY][3], xn[TY][3], lo[2][3], lox[2][3], up[3], upx[3];
+        R own[FH][3], xn[FH][3], lo[2][3], lox[2][3], up[3], upx[3];
 #pragma unroll
-        for (int ly = 0; ly < TY; ++ly) {
+        for (int r = 0; r < FH; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                own[ly][c] = io[c * BP + cxo + (ly + 1) * PX];
-                xn[ly][c] = ixn[c * BP + cxn + (ly + 1) * PX];
+                own[r][c] = io[c * BP + cxo + (ly0 + r + 1) * PX];
+                xn[r][c] = ixn[c * BP + cxn + (ly0 + r + 1) * PX];
             }
         }
+        // the lower image reaches rows 0 and 1, the upper one row 15
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                lo[r][c] = il[c * BP + cxo + (r + hl + 1) * PX];
-                lox[r][c] = ilx[c * BP + cxn + (r + hl + 1) * PX];
+                lo[r][c] = half ? R(0) : il[c * BP + cxo + (r + hl + 1) * PX];
+                lox[r][c] = half ? R(0) : ilx[c * BP + cxn + (r + hl + 1) * PX];
             }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            up[c] = iu[c * BP + cxo];
-            upx[c] = iux[c * BP + cxn];
+            up[c] = half ? iu[c * BP + cxo] : R(0);
+            upx[c] = half ? iux[c * BP + cxn] : R(0);
         }
         // one level of images: the x neighbour first when it lies to the left
         auto level = [&](R &a, R o, R n) {
@@ -823,20 +829,21 @@ __global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
             a += xo < 0 ? o : (xo > 0 ? n : R(0));
         };
 #pragma unroll
-        for (int ly = 0; ly < TY; ++ly) {
+        for (int r = 0; r < FH; ++r) {
+            const int ly = ly0 + r;
             const size_t g = (size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 R a = 0;
-                if (ly < 2) level(a, lo[ly][c], lox[ly][c]);
-                level(a, own[ly][c], xn[ly][c]);
-                if (ly == TY - 1) level(a, up[c], upx[c]);
+                if (!half && r < 2) level(a, lo[r][c], lox[r][c]);
+                level(a, own[r][c], xn[r][c]);
+                if (half && r == FH - 1) level(a, up[c], upx[c]);
                 glob(out[c])[g] = gap ? R(0) : a;
             }
         }
         return;
     }
-    for (int ly = 0; ly < h; ++ly) {
+    for (int ly = ly0; ly < ly1; ++ly) {
         R a[3] = {0, 0, 0};
         for (int oy = -1; oy <= 1; ++oy) {
             const int tyn = wrapi(ty + oy, d.nty);
@@ -1674,7 +1681,7 @@ template <typename R>
 hipError_t Launch<R>::fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s)
 {
     if (nplanes == 3) {
-        hipLaunchKernelGGL(k_fold_s<R>, dim3(((d.ntx + 3) / 4) * d.nty), dim3(64), 0, s, d, o0,
+        hipLaunchKernelGGL(k_fold_s<R>, dim3(((d.ntx + 3) / 4) * d.nty * 2), dim3(64), 0, s, d, o0,
                            o1, o2);
         return hipGetLastError();
     }
