@@ -971,7 +971,7 @@ __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const
 // (B half at i - 1) and lanes beyond the strip (E at i + 1, i + 2): lanes
 // P .. 62 - P end with complete results.  The arithmetic is that of
 // filter_body and yee_body, term for term.
-constexpr int YS_S = 8;
+constexpr int YS_S = 6;
 
 // Output columns of one wavefront of k_yee_s<R, RF>.
 __host__ __device__ constexpr int yee_strip_w(int rf) { return 63 - 2 * (rf > 1 ? rf : 1); }
