@@ -104,6 +104,11 @@ CASES = {
     "odd_66x66_three": (two_species(66, 66, 6.6, 6.6, filter_passes=3), False, False),
     "odd_62x31_four": (two_species(62, 31, 6.2, 3.1, filter_passes=4), False, False),
     "narrow_3x70": (two_species(3, 70, 0.3, 7.0, filter_passes=1), False, False),
+    # the FP64 instances of the streaming kernels, filter halos 1, 3 and 4
+    "odd_67x9_fp64": (two_species(67, 9, 6.7, 0.9, filter_passes=1), True, False),
+    "two_passes_comp_130x40_fp64": (two_species(130, 40, 13.0, 4.0, filter_passes=2,
+                                                filter_compensate=True), True, False),
+    "odd_62x31_four_fp64": (two_species(62, 31, 6.2, 3.1, filter_passes=4), True, False),
     "window_121x23": (two_species(121, 23, 2.42, 4.6, dt=0.014, moving_window=True,
                                   filter_passes=2, filter_compensate=True), False, False),
     "single_tile_4x4": (two_species(4, 4, 0.4, 0.4, filter_passes=1), False, False),
