@@ -350,9 +350,10 @@ int timed(pic_sim *s, int kind, hipStream_t st, Fn fn)
 
 // Append pending leavers to their tiles (no-op when none are pending).
 template <typename R>
-int enqueue_settle(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool only_if_shift = false)
+int enqueue_settle(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool only_if_shift = false,
+                   bool unpend = true)
 {
-    return timed(s, 1, st, [&] { return Launch<R>::settle(d, st, only_if_shift); });
+    return timed(s, 1, st, [&] { return Launch<R>::settle(d, st, only_if_shift, unpend); });
 }
 
 // a1-a4: push + deposit; the leavers are then appended to their new tiles
@@ -379,8 +380,9 @@ int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
     if (rc) return rc;
     if (d.window) {
         // the column shift needs every particle in its tile; without a shift
-        // the next push takes the pending leavers from the outboxes itself
-        rc = enqueue_settle(s, d, st, true);
+        // the next push takes the pending leavers from the outboxes itself.
+        // The window launch clears the pending flag after a settle.
+        rc = enqueue_settle(s, d, st, true, false);
         if (rc) return rc;
         rc = timed(s, 5, st, [&] { return Launch<R>::window(d, st); });
     }

@@ -220,8 +220,10 @@ hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, h
 // Launchers (defined in pic_kernels.hip for R = float and double).
 template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
-    // only_if_shift: skip unless the last step shifted the moving window
-    static hipError_t settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift = false);
+    // only_if_shift: skip unless the last step shifted the moving window;
+    // unpend = false leaves clearing the pending flag to the window launch
+    static hipError_t settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift = false,
+                             bool unpend = true);
     static hipError_t fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s);
     // before_shift (three planes only): keep the window gap of the last
     // step's deposit although that step's end has shifted the window

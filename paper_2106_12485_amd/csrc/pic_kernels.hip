@@ -1111,15 +1111,18 @@ __device__ __forceinline__ void step_end_body(const SimDev<R> &d)
 // Row a8, part 1 (blocks [0, nty*nsp)): particles of the column that left the
 // window are removed by a stable in-tile compaction; part 2 (block nty*nsp):
 // the six field planes of that column are cleared.  No-op unless shifted.
+// With unpend, the field block also clears the pending flag of a hand-off
+// that k_settle has just completed.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_window_clear(SimDev<R> d)
+__device__ __forceinline__ void window_clear_body(const SimDev<R> &d, const int blk, bool unpend)
 {
     __shared__ int s_w[NT / 64];
-    const DevState *st = d.st;
+    DevState *st = d.st;
     if (!st->shift) return;
     const int col = wrapi(st->origin - 1, d.nxs);
     const int par = st->parity;
-    if ((int)blockIdx.x == d.nty * d.nsp) {
+    if (blk == d.nty * d.nsp) {
+        if (unpend && threadIdx.x == 0) st->pend = 0;
         for (int j = threadIdx.x; j < d.ny; j += NT) {
             const size_t g = (size_t)col + (size_t)j * d.nxs;
 #pragma unroll
@@ -1127,7 +1130,7 @@ __global__ __launch_bounds__(NT) void k_window_clear(SimDev<R> d)
         }
         return;
     }
-    const int ty = blockIdx.x % d.nty, s = blockIdx.x / d.nty;
+    const int ty = blk % d.nty, s = blk / d.nty;
     const int t = col / TX + ty * d.ntx;
     const SpDev<R> &S = d.sp[s];
     const PartBuf<R> &P = S.pb[st->ppar];
@@ -1165,16 +1168,22 @@ __global__ __launch_bounds__(NT) void k_window_clear(SimDev<R> d)
     if (threadIdx.x == 0) P.count[t] = kept;
 }
 
+template <typename R>
+__global__ __launch_bounds__(NT) void k_window_clear(SimDev<R> d)
+{
+    window_clear_body(d, blockIdx.x, false);
+}
+
 // Row a8, part 3: load the column that entered at the right edge.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
+__device__ __forceinline__ void window_inject_body(const SimDev<R> &d, const int blk)
 {
     __shared__ int s_w[NT / 64];
     const DevState *st = d.st;
     if (!st->shift) return;
     const int col = wrapi(st->origin + d.nx - 1, d.nxs);
     const long long ilab = (long long)d.nx - 1 + st->nshift;
-    const int ty = blockIdx.x % d.nty, s = blockIdx.x / d.nty;
+    const int ty = blk % d.nty, s = blk / d.nty;
     const int t = col / TX + ty * d.ntx;
     const int y0 = ty * TY, h = min(TY, d.ny - y0);
     const SpDev<R> &S = d.sp[s];
@@ -1221,6 +1230,26 @@ __global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
         added += tot;
     }
     if (threadIdx.x == 0) P.count[t] = min(n0 + added, cap);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_window_inject(SimDev<R> d)
+{
+    window_inject_body(d, blockIdx.x);
+}
+
+// Both parts of the shift in one launch, and the pending flag of the
+// preceding hand-off cleared: blocks [0, nty*nsp] clear, the rest inject.
+// The leaving and the entering column lie at least nx cells apart both ways
+// round the ring, so with nx >= 16 they are in different tiles.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_window(SimDev<R> d)
+{
+    const int a = d.nty * d.nsp;
+    if ((int)blockIdx.x <= a)
+        window_clear_body(d, blockIdx.x, true);
+    else
+        window_inject_body(d, (int)blockIdx.x - a - 1);
 }
 
 // Initial load of species s, one block per tile.  Particles are stored
@@ -1666,13 +1695,15 @@ hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 }
 
 template <typename R>
-hipError_t Launch<R>::settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift)
+hipError_t Launch<R>::settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift,
+                             bool unpend)
 {
     if (d.nsp > 0) {
         hipLaunchKernelGGL(k_settle<R>, dim3(d.ntiles), dim3(MT), 0, s, d, (int)only_if_shift);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (!unpend) return hipSuccess;
     hipLaunchKernelGGL(k_unpend<R>, dim3(1), dim3(64), 0, s, d, (int)only_if_shift);
     return hipGetLastError();
 }
@@ -1739,6 +1770,13 @@ hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
 template <typename R>
 hipError_t Launch<R>::window(const SimDev<R> &d, hipStream_t s)
 {
+    if (d.nx >= TX) {
+        hipLaunchKernelGGL(k_window<R>, dim3(2 * d.nty * d.nsp + 1), dim3(NT), 0, s, d);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_unpend<R>, dim3(1), dim3(64), 0, s, d, 1);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL(k_window_clear<R>, dim3(d.nty * d.nsp + 1), dim3(NT), 0, s, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d.nsp == 0) return e;
