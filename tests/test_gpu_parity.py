@@ -119,6 +119,9 @@ CASES = {
                                  filter_passes=1, filter_compensate=True), False, False),
     "window_60x20_fp64": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
                                       filter_passes=1, filter_compensate=True), True, True),
+    # a window narrower than a tile: the shift takes its separate launches
+    "window_12x20": (two_species(12, 20, 0.24, 4.0, dt=0.014, moving_window=True,
+                                 filter_passes=1, filter_compensate=True), False, False),
 }
 
 
