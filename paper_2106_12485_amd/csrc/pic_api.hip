@@ -943,11 +943,16 @@ struct pic_batch {
     SimDev<float> *d_table = nullptr;
     BatchDev *d_batch = nullptr;
     int2 *d_work = nullptr;
+    int2 *d_fwork = nullptr;  // units of the streaming fold
+    int2 *d_ywork = nullptr;  // units of the streaming filter + Yee
     SimDev<float> *h_table = nullptr;  // pinned staging
     BatchDev *h_batch = nullptr;
     int2 *h_work = nullptr;
+    int2 *h_fwork = nullptr;
+    int2 *h_ywork = nullptr;
     std::vector<unsigned long long> cur;  // uids of the staged simulations
-    int grid = 0;
+    int grid = 0, grid_fold = 0, grid_yee = 0;
+    int rf = -2;  // filter halo of the captured graph (-1: tile forms)
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -955,8 +960,13 @@ struct pic_batch {
 
 namespace {
 
+// Units of the streaming field kernels per simulation: the fold's are at
+// most 2 ntx nty + 2 nty <= 4 ntiles, the filter + Yee's at most ntx * 3 nty
+// (strips of >= 55 columns and 6 rows), so lists of 4 max_tiles hold both.
+constexpr int SUNITS_PER_TILE = 4;
+
 void batch_layout(int max_sims, long long max_tiles, size_t *o_table, size_t *o_batch,
-                  size_t *o_work, size_t *total)
+                  size_t *o_work, size_t *o_fwork, size_t *o_ywork, size_t *total)
 {
     size_t o = 0;
     *o_table = o;
@@ -965,6 +975,10 @@ void batch_layout(int max_sims, long long max_tiles, size_t *o_table, size_t *o_
     o = align256(o + sizeof(BatchDev));
     *o_work = o;
     o = align256(o + (size_t)max_tiles * sizeof(int2));
+    *o_fwork = o;
+    o = align256(o + (size_t)max_tiles * SUNITS_PER_TILE * sizeof(int2));
+    *o_ywork = o;
+    o = align256(o + (size_t)max_tiles * SUNITS_PER_TILE * sizeof(int2));
     *total = o;
 }
 
@@ -975,8 +989,8 @@ extern "C" {
 size_t pic_batch_mem_bytes(int max_sims, long long max_tiles)
 {
     if (max_sims < 1 || max_tiles < 1) return 0;
-    size_t a, b, c, t;
-    batch_layout(max_sims, max_tiles, &a, &b, &c, &t);
+    size_t a, b, c, f, y, t;
+    batch_layout(max_sims, max_tiles, &a, &b, &c, &f, &y, &t);
     return t;
 }
 
@@ -989,6 +1003,8 @@ int pic_batch_free(pic_batch *b)
     if (b->h_table) (void)hipHostFree(b->h_table);
     if (b->h_batch) (void)hipHostFree(b->h_batch);
     if (b->h_work) (void)hipHostFree(b->h_work);
+    if (b->h_fwork) (void)hipHostFree(b->h_fwork);
+    if (b->h_ywork) (void)hipHostFree(b->h_ywork);
     delete b;
     return PIC_OK;
 }
@@ -1000,8 +1016,8 @@ int pic_batch_create(void *arena, size_t arena_bytes, int max_sims, long long ma
     *out = nullptr;
     if (!arena || ((uintptr_t)arena & 255) || max_sims < 1 || max_tiles < 1)
         return fail(PIC_E_ARG, "bad batch arena or sizes");
-    size_t ot, ob, ow, total;
-    batch_layout(max_sims, max_tiles, &ot, &ob, &ow, &total);
+    size_t ot, ob, ow, of, oy, total;
+    batch_layout(max_sims, max_tiles, &ot, &ob, &ow, &of, &oy, &total);
     if (arena_bytes < total) return fail(PIC_E_NOMEM, "batch arena too small");
     pic_batch *b = new pic_batch();
     b->arena = (char *)arena;
@@ -1010,9 +1026,14 @@ int pic_batch_create(void *arena, size_t arena_bytes, int max_sims, long long ma
     b->d_table = (SimDev<float> *)(b->arena + ot);
     b->d_batch = (BatchDev *)(b->arena + ob);
     b->d_work = (int2 *)(b->arena + ow);
+    b->d_fwork = (int2 *)(b->arena + of);
+    b->d_ywork = (int2 *)(b->arena + oy);
     hipError_t e = hipHostMalloc((void **)&b->h_table, (size_t)max_sims * sizeof(SimDev<float>));
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_batch, sizeof(BatchDev));
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_work, (size_t)max_tiles * sizeof(int2));
+    const size_t su = (size_t)max_tiles * SUNITS_PER_TILE * sizeof(int2);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_fwork, su);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_ywork, su);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         pic_batch_free(b);
@@ -1040,35 +1061,65 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
             nwork += s->L.ntiles;
         }
         if (nwork > b->max_tiles) return fail(PIC_E_ARG, "batch work list too long");
+        // the streaming field kernels need one filter halo for the whole batch
+        int rf = -1;
+        for (int i = 0; i < n; ++i) {
+            const pic_cfg &c = sims[i]->cfg;
+            const int r = c.filter_passes > 0 ? c.filter_passes + (c.filter_compensate ? 1 : 0) : 0;
+            rf = i == 0 ? r : (r == rf ? rf : -1);
+            if (rf < 0) break;
+        }
         // the staging buffers may still feed an earlier copy
         HIPCHK(hipStreamSynchronize(st));
-        long long w = 0;
+        long long w = 0, wf = 0, wy = 0;
         for (int i = 0; i < n; ++i) {
+            const Layout &L = sims[i]->L;
             b->h_table[i] = sims[i]->df;
-            for (int t = 0; t < sims[i]->L.ntiles; ++t) b->h_work[w++] = make_int2(i, t);
+            for (int t = 0; t < L.ntiles; ++t) b->h_work[w++] = make_int2(i, t);
+            if (rf >= 0) {
+                const int nf = fold_units(L.ntx, L.nty), ny = yee_units(L.nxs, sims[i]->cfg.ny, rf);
+                if (wf + nf > b->max_tiles * SUNITS_PER_TILE || wy + ny > b->max_tiles * SUNITS_PER_TILE)
+                    return fail(PIC_E_ARG, "batch work list too long");
+                for (int u = 0; u < nf; ++u) b->h_fwork[wf++] = make_int2(i, u);
+                for (int u = 0; u < ny; ++u) b->h_ywork[wy++] = make_int2(i, u);
+            }
         }
         b->h_batch->nwork = (int)nwork;
         b->h_batch->nsim = n;
         b->h_batch->work = b->d_work;
         b->h_batch->blocks_done = 0;
+        b->h_batch->nfold = (int)wf;
+        b->h_batch->nyee = (int)wy;
+        b->h_batch->fold_work = b->d_fwork;
+        b->h_batch->yee_work = b->d_ywork;
         HIPCHK(hipMemcpyAsync(b->d_table, b->h_table, (size_t)n * sizeof(SimDev<float>),
                               hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(b->d_work, b->h_work, (size_t)nwork * sizeof(int2),
                               hipMemcpyHostToDevice, st));
+        if (rf >= 0) {
+            HIPCHK(hipMemcpyAsync(b->d_fwork, b->h_fwork, (size_t)wf * sizeof(int2),
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(b->d_ywork, b->h_ywork, (size_t)wy * sizeof(int2),
+                                  hipMemcpyHostToDevice, st));
+        }
         HIPCHK(hipMemcpyAsync(b->d_batch, b->h_batch, sizeof(BatchDev), hipMemcpyHostToDevice,
                               st));
         b->cur.resize(n);
         for (int i = 0; i < n; ++i) b->cur[i] = sims[i]->uid;
         // one graph serves every work list up to its grid; blocks past the
         // work count exit at once
-        const int need = (int)((nwork + 1023) / 1024 * 1024);
-        if (!b->gexec || need > b->grid || b->grid > 4 * need) {
+        auto round = [](long long v) { return (int)((v + 1023) / 1024 * 1024); };
+        const int need = round(nwork), need_f = round(wf), need_y = round(wy);
+        auto fits = [](int need_, int grid_) { return need_ <= grid_ && grid_ <= 4 * need_; };
+        if (!b->gexec || rf != b->rf || !fits(need, b->grid) ||
+            (rf >= 0 && (!fits(need_f, b->grid_fold) || !fits(need_y, b->grid_yee)))) {
             if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
             if (b->graph) (void)hipGraphDestroy(b->graph);
             b->gexec = nullptr;
             b->graph = nullptr;
             HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
-            hipError_t le = launch_batch_step<float>(b->d_table, b->d_batch, need, b->cap_stream);
+            hipError_t le = launch_batch_step<float>(b->d_table, b->d_batch, need, b->cap_stream,
+                                                     rf, need_f, need_y);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
             if (le != hipSuccess || ce != hipSuccess)
@@ -1076,6 +1127,9 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
             b->graph = g;
             HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
             b->grid = need;
+            b->grid_fold = need_f;
+            b->grid_yee = need_y;
+            b->rf = rf;
         }
     }
     for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(b->gexec, st));

@@ -29,7 +29,18 @@ constexpr int NT = 256;             // threads per block (4 wavefronts)
 constexpr int NTP = 512;            // threads per push block (8 wavefronts)
 constexpr int NTB = 512;            // threads per batched push block
 constexpr int MAX_SP = 4;
-constexpr int MAX_FR = 4;           // largest filter halo (passes + compensator)
+constexpr int MAX_FR = 4;
+// Streaming field kernels: the fold takes half a tile row (FH rows) of four
+// tiles per wavefront, the filter + Yee a strip of YS_S rows and
+// yee_strip_w(rf) columns (rf = filter passes + compensator).
+constexpr int FH = 8;
+constexpr int YS_S = 6;
+__host__ __device__ constexpr int yee_strip_w(int rf) { return 63 - 2 * (rf > 1 ? rf : 1); }
+__host__ __device__ constexpr int fold_units(int ntx, int nty) { return ((ntx + 3) / 4) * nty * 2; }
+__host__ __device__ constexpr int yee_units(int nxs, int ny, int rf)
+{
+    return ((nxs + yee_strip_w(rf) - 1) / yee_strip_w(rf)) * ((ny + YS_S - 1) / YS_S);
+}           // largest filter halo (passes + compensator)
 constexpr int QX = TX + 2 * MAX_FR; // LDS pitch of the filter block
 constexpr int QY = TY + 2 * MAX_FR;
 constexpr int ERR_CAPACITY = 1;
@@ -213,9 +224,15 @@ struct BatchDev {
     int nsim;         // descriptors in use
     const int2 *work; // (simulation, tile), simulations in contiguous runs
     int blocks_done;  // blocks of the running launch that finished
+    // streaming field kernels (when every simulation has the same filter
+    // halo): (simulation, unit) lists of the fold and of the filter + Yee
+    int nfold, nyee;
+    const int2 *fold_work;
+    const int2 *yee_work;
 };
 template <typename R>
-hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s);
+hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s,
+                             int rf = -1, int grid_fold = 0, int grid_yee = 0);
 
 // Launchers (defined in pic_kernels.hip for R = float and double).
 template <typename R> struct Launch {

@@ -768,13 +768,11 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
 // 15): all of the wavefront's loads go out first, unconditionally (a lane
 // that needs no neighbour reads its own entry again and adds zero), then the
 // sums.  Other tiles take the general per-cell path.
-constexpr int FH = TY / 2;  // rows of a tile row per wavefront of k_fold_s
-
 template <typename R>
-__global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
+__device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R *o0, R *o1,
+                                            R *o2)
 {
     const int ngx = (d.ntx + 3) / 4;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
     // rows FH * half .. of tile row ty
     const int rg = blk / ngx, ty = rg >> 1, half = rg & 1;
     const int tx = (blk % ngx) * 4 + (int)(threadIdx.x >> 4);
@@ -864,6 +862,24 @@ __global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
 #pragma unroll
         for (int c = 0; c < 3; ++c) glob(out[c])[g] = gap ? R(0) : a[c];
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
+{
+    fold_s_body(d, xcd_remap(blockIdx.x, gridDim.x), o0, o1, o2);
+}
+
+// the same over a batch: work list entries (simulation, unit)
+template <typename R>
+__global__ __launch_bounds__(64) void k_fold_sb(const SimDev<R> *__restrict__ ds,
+                                                const BatchDev *__restrict__ b)
+{
+    const int n = __builtin_amdgcn_readfirstlane(b->nfold);
+    if ((int)blockIdx.x >= n) return;
+    const int2 w = b->fold_work[xcd_remap(blockIdx.x, n)];
+    const SimDev<R> &d = ds[__builtin_amdgcn_readfirstlane(w.x)];
+    fold_s_body(d, __builtin_amdgcn_readfirstlane(w.y), d.J[0], d.J[1], d.J[2]);
 }
 
 // Row a6 in streaming form, for the three current planes of one simulation
@@ -971,20 +987,14 @@ __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const
 // (B half at i - 1) and lanes beyond the strip (E at i + 1, i + 2): lanes
 // P .. 62 - P end with complete results.  The arithmetic is that of
 // filter_body and yee_body, term for term.
-constexpr int YS_S = 6;
-
-// Output columns of one wavefront of k_yee_s<R, RF>.
-__host__ __device__ constexpr int yee_strip_w(int rf) { return 63 - 2 * (rf > 1 ? rf : 1); }
-
 template <typename R, int RF>
-__global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
+__device__ __forceinline__ void yee_s_body(const SimDev<R> &d, const int blk)
 {
     // no contraction into fma: the tile and streaming forms (and the batched
     // launches) must round every term alike
 #pragma clang fp contract(off)
     constexpr int P = RF > 1 ? RF : 1, W = yee_strip_w(RF);
     const int ncg = (d.nxs + W - 1) / W;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int cg = blk % ncg, r0 = (blk / ncg) * YS_S;
     const int nr = min(YS_S, d.ny - r0);
     const int L = threadIdx.x;
@@ -1070,6 +1080,23 @@ __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
             glob(npar ? d.F[1][5] : d.F[0][5])[g] = nbz;
         }
     }
+}
+
+template <typename R, int RF>
+__global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
+{
+    yee_s_body<R, RF>(d, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// the same over a batch whose simulations share the filter halo RF
+template <typename R, int RF>
+__global__ __launch_bounds__(64) void k_yee_sb(const SimDev<R> *__restrict__ ds,
+                                               const BatchDev *__restrict__ b)
+{
+    const int n = __builtin_amdgcn_readfirstlane(b->nyee);
+    if ((int)blockIdx.x >= n) return;
+    const int2 w = b->yee_work[xcd_remap(blockIdx.x, n)];
+    yee_s_body<R, RF>(ds[__builtin_amdgcn_readfirstlane(w.x)], __builtin_amdgcn_readfirstlane(w.y));
 }
 
 // True in thread 0 of the block that finishes a launch last: every block
@@ -1712,7 +1739,7 @@ template <typename R>
 hipError_t Launch<R>::fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s)
 {
     if (nplanes == 3) {
-        hipLaunchKernelGGL(k_fold_s<R>, dim3(((d.ntx + 3) / 4) * d.nty * 2), dim3(64), 0, s, d, o0,
+        hipLaunchKernelGGL(k_fold_s<R>, dim3(fold_units(d.ntx, d.nty)), dim3(64), 0, s, d, o0,
                            o1, o2);
         return hipGetLastError();
     }
@@ -1749,17 +1776,15 @@ template <typename R>
 hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
 {
     const int rf = d.npass > 0 ? d.npass + (d.compensate ? 1 : 0) : 0;
-    const int nsy = (d.ny + YS_S - 1) / YS_S;
-    auto go = [&](auto kern, int w) {
-        hipLaunchKernelGGL(kern, dim3(((d.nxs + w - 1) / w) * nsy), dim3(64), 0, s, d);
-    };
+    const dim3 grid(yee_units(d.nxs, d.ny, rf));
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, d); };
     static_assert(MAX_FR == 4, "one instance per filter halo");
     switch (rf) {
-    case 0: go(k_yee_s<R, 0>, yee_strip_w(0)); break;
-    case 1: go(k_yee_s<R, 1>, yee_strip_w(1)); break;
-    case 2: go(k_yee_s<R, 2>, yee_strip_w(2)); break;
-    case 3: go(k_yee_s<R, 3>, yee_strip_w(3)); break;
-    default: go(k_yee_s<R, 4>, yee_strip_w(4)); break;
+    case 0: go(k_yee_s<R, 0>); break;
+    case 1: go(k_yee_s<R, 1>); break;
+    case 2: go(k_yee_s<R, 2>); break;
+    case 3: go(k_yee_s<R, 3>); break;
+    default: go(k_yee_s<R, 4>); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1828,20 +1853,37 @@ hipError_t Launch<R>::copy_plane(const R *src, R *dst, long long n, hipStream_t 
 // One step of a batch: grid = the work-list capacity the graph was captured
 // for; `ds` and `b` live in device memory.
 template <typename R>
-hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s)
+hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, hipStream_t s,
+                             int rf, int grid_fold, int grid_yee)
 {
     hipLaunchKernelGGL(k_push_deposit_b<R>, dim3(grid), dim3(NTB), 0, s, ds, b);
-    hipLaunchKernelGGL(k_fold_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
-    hipLaunchKernelGGL(k_filter_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
-    hipLaunchKernelGGL(k_yee_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    if (rf >= 0 && rf <= MAX_FR) {
+        // the streaming forms, when every simulation has the same filter halo
+        hipLaunchKernelGGL(k_fold_sb<R>, dim3(grid_fold), dim3(64), 0, s, ds, b);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid_yee), dim3(64), 0, s, ds, b);
+        };
+        static_assert(MAX_FR == 4, "one instance per filter halo");
+        switch (rf) {
+        case 0: go(k_yee_sb<R, 0>); break;
+        case 1: go(k_yee_sb<R, 1>); break;
+        case 2: go(k_yee_sb<R, 2>); break;
+        case 3: go(k_yee_sb<R, 3>); break;
+        default: go(k_yee_sb<R, 4>); break;
+        }
+    } else {
+        hipLaunchKernelGGL(k_fold_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+        hipLaunchKernelGGL(k_filter_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+        hipLaunchKernelGGL(k_yee_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
+    }
     hipLaunchKernelGGL(k_step_end_b<R>, dim3(1), dim3(64), 0, s, ds, b);
     return hipGetLastError();
 }
 
 template hipError_t launch_batch_step<float>(const SimDev<float> *, const BatchDev *, int,
-                                             hipStream_t);
+                                             hipStream_t, int, int, int);
 template hipError_t launch_batch_step<double>(const SimDev<double> *, const BatchDev *, int,
-                                              hipStream_t);
+                                              hipStream_t, int, int, int);
 
 template struct Launch<float>;
 template struct Launch<double>;
