@@ -157,6 +157,11 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->npass = c->filter_passes;
     d->compensate = c->filter_compensate ? 1 : 0;
     d->direct = c->deposit_mode == 1 ? 1 : 0;
+    // push block size from the initial load of a full tile
+    long long per_tile = 0;
+    for (int s = 0; s < c->n_species; ++s)
+        per_tile += (long long)c->sp[s].ppc_x * c->sp[s].ppc_y * TX * TY;
+    d->push_bt = per_tile >= BIG_TILE ? NTP_BIG : NTP;
     d->dx_d = c->lx / c->nx;
     d->dy_d = c->ly / c->ny;
     d->dt_d = c->dt;

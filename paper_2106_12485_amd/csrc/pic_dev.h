@@ -27,6 +27,8 @@ constexpr int PY = TY + 3;
 constexpr int BP = PX * PY;         // cells of a tile block
 constexpr int NT = 256;             // threads per block (4 wavefronts)
 constexpr int NTP = 512;            // threads per push block (8 wavefronts)
+constexpr int NTP_BIG = 1024;       // ... for tiles loaded with >= BIG_TILE particles
+constexpr int BIG_TILE = 65536;
 constexpr int NTB = 512;            // threads per batched push block
 constexpr int MAX_SP = 4;
 constexpr int MAX_FR = 4;
@@ -103,6 +105,7 @@ struct SimDev {
     int nx, ny, nxs;
     int ntx, nty, ntiles;
     int window, nsp, cap_out;
+    int push_bt;      // threads per single-simulation push block: NTP or NTP_BIG
     int npass, compensate;
     int direct;       // 1: colour-phased deposit straight into J (no fold)
     R dx, dy, dt;

@@ -1594,11 +1594,14 @@ __device__ __forceinline__ bool batch_item(const BatchDev *__restrict__ b, int2 
 template <typename R> struct PushWaves { static constexpr int n = 8; };
 template <> struct PushWaves<double> { static constexpr int n = 4; };
 
-template <typename R>
-__global__ __launch_bounds__(NTP) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
+// Tiles that hold many particles (the Weibel run's 131,072) take blocks of
+// NTP_BIG threads: a tile's work then spreads over twice the wavefronts,
+// which shortens the launch most when the particles pile up in a few tiles.
+template <typename R, int BT>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
 k_push_deposit(SimDev<R> d)
 {
-    push_body<NTP, false>(d, xcd_remap(blockIdx.x, gridDim.x));
+    push_body<BT, false>(d, xcd_remap(blockIdx.x, gridDim.x));
     if (last_block(&d.st->blocks_done)) push_end_body(d);
 }
 
@@ -1717,7 +1720,10 @@ hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
         }
         return e;
     }
-    hipLaunchKernelGGL(k_push_deposit<R>, dim3(d.ntiles), dim3(NTP), 0, s, d);
+    if (d.push_bt == NTP_BIG)
+        hipLaunchKernelGGL((k_push_deposit<R, NTP_BIG>), dim3(d.ntiles), dim3(NTP_BIG), 0, s, d);
+    else
+        hipLaunchKernelGGL((k_push_deposit<R, NTP>), dim3(d.ntiles), dim3(NTP), 0, s, d);
     return hipGetLastError();
 }
 

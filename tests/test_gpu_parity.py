@@ -119,6 +119,12 @@ CASES = {
                                  filter_passes=1, filter_compensate=True), False, False),
     "window_60x20_fp64": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
                                       filter_passes=1, filter_compensate=True), True, True),
+    # 2 x 256 particles per cell: tiles loaded past 65,536 take 1024-thread push blocks
+    "big_tiles_36x34": (Workload("big", 36, 34, 3.6, 3.4, 0.07, 1,
+                                 [SpeciesSpec(-1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3),
+                                  SpeciesSpec(1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3,
+                                              ufl=(0.0, 0.0, 0.5))],
+                                 filter_passes=1), False, False),
     # a window narrower than a tile: the shift takes its separate launches
     "window_12x20": (two_species(12, 20, 0.24, 4.0, dt=0.014, moving_window=True,
                                  filter_passes=1, filter_compensate=True), False, False),
