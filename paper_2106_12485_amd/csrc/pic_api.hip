@@ -44,6 +44,7 @@ struct Layout {
     int nxs, ntx, nty, ntiles;
     int cap[MAX_SP];
     int cap_out;
+    int push_bt, nsb;  // threads per push block; push blocks per tile
     size_t rs;  // bytes of the working precision
     size_t plane;  // elements of one storage plane
     size_t off_state, off_F, off_J, off_Jf, off_rho, off_rho_f, off_rho_prev, off_g0, off_blk,
@@ -120,7 +121,15 @@ int layout(const pic_cfg *c, Layout *L)
     L->off_rho_f = take(L->plane * L->rs);
     L->off_rho_prev = take(L->plane * L->rs);
     L->off_g0 = take(L->plane * 8);
-    L->off_blk = take((size_t)L->ntiles * 3 * BP * L->rs);
+    // Tiles loaded with BIG_TILE particles or more take 1024-thread push
+    // blocks and, with several species, one block per species, each leaving
+    // its current as exact 64-bit sums (see push_body).
+    long long per_tile = 0;
+    for (int s = 0; s < c->n_species; ++s)
+        per_tile += (long long)c->sp[s].ppc_x * c->sp[s].ppc_y * TX * TY;
+    L->push_bt = per_tile >= BIG_TILE ? NTP_BIG : NTP;
+    L->nsb = per_tile >= BIG_TILE && c->deposit_mode == 0 && c->n_species > 1 ? c->n_species : 1;
+    L->off_blk = take((size_t)L->ntiles * 3 * BP * (L->nsb > 1 ? L->nsb * 8 : L->rs));
     L->off_red = take(((size_t)NB_DIAG * 5 + (size_t)L->ntiles * MAX_SP) * 8);
     L->off_res = take(N_RED * 8);
     const size_t obs = (size_t)L->ntiles * L->cap_out;
@@ -157,11 +166,8 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->npass = c->filter_passes;
     d->compensate = c->filter_compensate ? 1 : 0;
     d->direct = c->deposit_mode == 1 ? 1 : 0;
-    // push block size from the initial load of a full tile
-    long long per_tile = 0;
-    for (int s = 0; s < c->n_species; ++s)
-        per_tile += (long long)c->sp[s].ppc_x * c->sp[s].ppc_y * TX * TY;
-    d->push_bt = per_tile >= BIG_TILE ? NTP_BIG : NTP;
+    d->push_bt = L.push_bt;
+    d->nsb = L.nsb;
     d->dx_d = c->lx / c->nx;
     d->dy_d = c->ly / c->ny;
     d->dt_d = c->dt;
@@ -1080,6 +1086,7 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
         for (int i = 0; i < n; ++i) {
             const Layout &L = sims[i]->L;
             b->h_table[i] = sims[i]->df;
+            b->h_table[i].nsb = 1;  // batched pushes take every species of a tile at once
             for (int t = 0; t < L.ntiles; ++t) b->h_work[w++] = make_int2(i, t);
             if (rf >= 0) {
                 const int nf = fold_units(L.ntx, L.nty), ny = yee_units(L.nxs, sims[i]->cfg.ny, rf);

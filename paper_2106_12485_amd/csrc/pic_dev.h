@@ -106,6 +106,8 @@ struct SimDev {
     int ntx, nty, ntiles;
     int window, nsp, cap_out;
     int push_bt;      // threads per single-simulation push block: NTP or NTP_BIG
+    int nsb;          // push blocks per tile: 1, or one per species (blk then holds
+                      // nsb slices of 64-bit sums per tile)
     int npass, compensate;
     int direct;       // 1: colour-phased deposit straight into J (no fold)
     R dx, dy, dt;

@@ -192,8 +192,13 @@ __device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R
 // wavefront, and the ones that leave go to outbox opar ^ 1 with their
 // direction.  Particles leaving the moving window are dropped.
 // ---------------------------------------------------------------------------
+// g: with d.nsb > 1 species blocks per tile, this block pushes species g only
+// and leaves its current block as exact 64-bit sums in slice g of the tile
+// (the fold adds the slices as integers before converting, so the result is
+// the same bits as one block pushing every species).
 template <int BT, bool DIRECT, typename R>
-__device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
+__device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const int g = 0,
+                                          const int nsb = 1)
 {
     __shared__ R sf[6 * BP];
     __shared__ unsigned long long sj[3 * BP];
@@ -213,7 +218,8 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
     const unsigned long long below = (1ull << lane) - 1ull;
     const R jq = d.jq;
     const size_t obase = (size_t)t * d.cap_out;
-    for (int s = 0; s < d.nsp; ++s) {
+    const int s0 = nsb > 1 ? g : 0, s1 = nsb > 1 ? g + 1 : d.nsp;
+    for (int s = s0; s < s1; ++s) {
         const SpDev<R> &P = d.sp[s];
         neighbour_runs(d, P, t, ob, pend, s_nb, s_want, s_pre + 1);
         if (threadIdx.x == 0) {
@@ -421,6 +427,10 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
             const gptr<R> J = glob(d.J[c]);
             J[g] = J[g] + (R)fx_value(sj[k], jqi);
         }
+    } else if (nsb > 1) {
+        const gptr<unsigned long long> out = glob(
+            reinterpret_cast<unsigned long long *>(d.blk) + ((size_t)t * nsb + g) * 3 * BP);
+        for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = sj[k];
     } else {
         const gptr<R> out = glob(d.blk + (size_t)t * 3 * BP);
         for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = (R)fx_value(sj[k], jqi);
@@ -768,7 +778,7 @@ __device__ __forceinline__ void yee_body(const SimDev<R> &d, const int t)
 // 15): all of the wavefront's loads go out first, unconditionally (a lane
 // that needs no neighbour reads its own entry again and adds zero), then the
 // sums.  Other tiles take the general per-cell path.
-template <typename R>
+template <typename R, int NSB>
 __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R *o0, R *o1,
                                             R *o2)
 {
@@ -784,8 +794,17 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
     if (lx >= w || ly0 >= ly1) return;
     const bool gap = d.window && window_col(x0 + lx, glob(d.st)->origin, d.nxs) >= d.nx;
     R *const out[3] = {o0, o1, o2};
-    auto img = [&](int a, int b) {
-        return glob<const R>(d.blk + (size_t)(a + b * d.ntx) * 3 * BP);
+    // entry `off` of the image of tile (a, b): a float block, or NSB > 1
+    // slices of exact 64-bit sums added before the one conversion
+    auto img = [&](int a, int b) { return (size_t)(a + b * d.ntx); };
+    auto ent = [&](size_t tile, int off) -> R {
+        if (NSB == 1) return glob<const R>(d.blk)[tile * 3 * BP + off];
+        const gptr<const unsigned long long> q =
+            glob(reinterpret_cast<const unsigned long long *>(d.blk)) + tile * NSB * 3 * BP + off;
+        unsigned long long sum = 0;
+#pragma unroll
+        for (int g = 0; g < NSB; ++g) sum += q[(size_t)g * 3 * BP];
+        return (R)fx_value(sum, d.jq_inv);
     };
     if (h == TY && w >= 3) {
         const int txl = wrapi(tx - 1, d.ntx), txr = wrapi(tx + 1, d.ntx);
@@ -795,16 +814,16 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
         const int txn = xo < 0 ? txl : (xo > 0 ? txr : tx);
         // column (px + 1) of the cell in its own image and in the x neighbour's
         const int cxo = lx + 1, cxn = xo < 0 ? lx + wl + 1 : (xo > 0 ? 0 : lx + 1);
-        const gptr<const R> io = img(tx, ty), ixn = img(txn, ty);
-        const gptr<const R> il = img(tx, tyl), ilx = img(txn, tyl);
-        const gptr<const R> iu = img(tx, tyu), iux = img(txn, tyu);
+        const size_t io = img(tx, ty), ixn = img(txn, ty);
+        const size_t il = img(tx, tyl), ilx = img(txn, tyl);
+        const size_t iu = img(tx, tyu), iux = img(txn, tyu);
         R own[FH][3], xn[FH][3], lo[2][3], lox[2][3], up[3], upx[3];
 #pragma unroll
         for (int r = 0; r < FH; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                own[r][c] = io[c * BP + cxo + (ly0 + r + 1) * PX];
-                xn[r][c] = ixn[c * BP + cxn + (ly0 + r + 1) * PX];
+                own[r][c] = ent(io, c * BP + cxo + (ly0 + r + 1) * PX);
+                xn[r][c] = ent(ixn, c * BP + cxn + (ly0 + r + 1) * PX);
             }
         }
         // the lower image reaches rows 0 and 1, the upper one row 15
@@ -812,14 +831,14 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
         for (int r = 0; r < 2; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                lo[r][c] = half ? R(0) : il[c * BP + cxo + (r + hl + 1) * PX];
-                lox[r][c] = half ? R(0) : ilx[c * BP + cxn + (r + hl + 1) * PX];
+                lo[r][c] = half ? R(0) : ent(il, c * BP + cxo + (r + hl + 1) * PX);
+                lox[r][c] = half ? R(0) : ent(ilx, c * BP + cxn + (r + hl + 1) * PX);
             }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            up[c] = half ? iu[c * BP + cxo] : R(0);
-            upx[c] = half ? iux[c * BP + cxn] : R(0);
+            up[c] = half ? ent(iu, c * BP + cxo) : R(0);
+            upx[c] = half ? ent(iux, c * BP + cxn) : R(0);
         }
         // one level of images: the x neighbour first when it lies to the left
         auto level = [&](R &a, R o, R n) {
@@ -853,9 +872,9 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
                 const int wn = min(TX, d.nxs - txn * TX);
                 const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
                 if (px < -1 || px >= wn + 2) continue;
-                const gptr<const R> b = img(txn, tyn);
+                const size_t b = img(txn, tyn);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) a[c] += b[c * BP + (px + 1) + (py + 1) * PX];
+                for (int c = 0; c < 3; ++c) a[c] += ent(b, c * BP + (px + 1) + (py + 1) * PX);
             }
         }
         const size_t g = (size_t)(x0 + lx) + (size_t)(y0 + ly) * d.nxs;
@@ -864,10 +883,10 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
     }
 }
 
-template <typename R>
+template <typename R, int NSB>
 __global__ __launch_bounds__(64) void k_fold_s(SimDev<R> d, R *o0, R *o1, R *o2)
 {
-    fold_s_body(d, xcd_remap(blockIdx.x, gridDim.x), o0, o1, o2);
+    fold_s_body<R, NSB>(d, xcd_remap(blockIdx.x, gridDim.x), o0, o1, o2);
 }
 
 // the same over a batch: work list entries (simulation, unit)
@@ -879,7 +898,8 @@ __global__ __launch_bounds__(64) void k_fold_sb(const SimDev<R> *__restrict__ ds
     if ((int)blockIdx.x >= n) return;
     const int2 w = b->fold_work[xcd_remap(blockIdx.x, n)];
     const SimDev<R> &d = ds[__builtin_amdgcn_readfirstlane(w.x)];
-    fold_s_body(d, __builtin_amdgcn_readfirstlane(w.y), d.J[0], d.J[1], d.J[2]);
+    // batches step every simulation with one block per tile (nsb = 1)
+    fold_s_body<R, 1>(d, __builtin_amdgcn_readfirstlane(w.y), d.J[0], d.J[1], d.J[2]);
 }
 
 // Row a6 in streaming form, for the three current planes of one simulation
@@ -1601,7 +1621,9 @@ template <typename R, int BT>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
 k_push_deposit(SimDev<R> d)
 {
-    push_body<BT, false>(d, xcd_remap(blockIdx.x, gridDim.x));
+    // the species blocks of a tile are neighbours in the dispatch order
+    const int i = xcd_remap(blockIdx.x, gridDim.x), nsb = d.nsb;
+    push_body<BT, false>(d, i / nsb, i % nsb, nsb);
     if (last_block(&d.st->blocks_done)) push_end_body(d);
 }
 
@@ -1720,10 +1742,11 @@ hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
         }
         return e;
     }
+    const dim3 grid(d.ntiles * d.nsb);
     if (d.push_bt == NTP_BIG)
-        hipLaunchKernelGGL((k_push_deposit<R, NTP_BIG>), dim3(d.ntiles), dim3(NTP_BIG), 0, s, d);
+        hipLaunchKernelGGL((k_push_deposit<R, NTP_BIG>), grid, dim3(NTP_BIG), 0, s, d);
     else
-        hipLaunchKernelGGL((k_push_deposit<R, NTP>), dim3(d.ntiles), dim3(NTP), 0, s, d);
+        hipLaunchKernelGGL((k_push_deposit<R, NTP>), grid, dim3(NTP), 0, s, d);
     return hipGetLastError();
 }
 
@@ -1745,8 +1768,15 @@ template <typename R>
 hipError_t Launch<R>::fold(const SimDev<R> &d, int nplanes, R *o0, R *o1, R *o2, hipStream_t s)
 {
     if (nplanes == 3) {
-        hipLaunchKernelGGL(k_fold_s<R>, dim3(fold_units(d.ntx, d.nty)), dim3(64), 0, s, d, o0,
-                           o1, o2);
+        const dim3 grid(fold_units(d.ntx, d.nty));
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, d, o0, o1, o2); };
+        static_assert(MAX_SP == 4, "one instance per species-block count");
+        switch (d.nsb) {
+        case 1: go(k_fold_s<R, 1>); break;
+        case 2: go(k_fold_s<R, 2>); break;
+        case 3: go(k_fold_s<R, 3>); break;
+        default: go(k_fold_s<R, 4>); break;
+        }
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_fold<R>, dim3(d.ntiles), dim3(NT), 0, s, d, nplanes, o0, o1, o2);
