@@ -125,6 +125,11 @@ CASES = {
                                   SpeciesSpec(1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3,
                                               ufl=(0.0, 0.0, 0.5))],
                                  filter_passes=1), False, False),
+    "big_tiles_36x34_fp64": (Workload("big", 36, 34, 3.6, 3.4, 0.07, 1,
+                                      [SpeciesSpec(-1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3),
+                                       SpeciesSpec(1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3,
+                                                   ufl=(0.0, 0.0, 0.5))],
+                                      filter_passes=1), True, False),
     # a window narrower than a tile: the shift takes its separate launches
     "window_12x20": (two_species(12, 20, 0.24, 4.0, dt=0.014, moving_window=True,
                                  filter_passes=1, filter_compensate=True), False, False),
