@@ -392,6 +392,185 @@ def test_kinetic_energy_closed_form_without_fields():
 
 
 # ---------------------------------------------------------------------------
+# the whole cycle against a second, naive implementation
+# ---------------------------------------------------------------------------
+def _hat(d, n):
+    """Linear (cloud-in-cell) weight of a node at signed distance d, in cells,
+    on a periodic ring of n cells."""
+    d = np.mod(d + n / 2, n) - n / 2
+    return np.maximum(0.0, 1.0 - np.abs(d))
+
+
+class _NaivePIC:
+    """The cycle of Sec. 2.2 (interpolate, Boris push, charge-conserving
+    deposit, binomial filter, Yee) written a second time from the definitions,
+    for a periodic box only and with nothing shared with the oracle:
+
+    - interpolation visits every node with its own weight (no corner search);
+    - the current is the exact time integral of charge x velocity x shape over
+      the straight path: the path is cut at every integer crossing of x or y,
+      the shape (cell indicator along the current, linear weight across it;
+      the product of two linear weights for Jz) is linear or quadratic on each
+      piece, so the midpoint rule, or Simpson's rule for Jz, is exact there;
+    - the filter and the curls are np.roll stencils on whole planes.
+    """
+
+    def __init__(self, nx, ny, dx, dy, dt, npass, comp):
+        self.nx, self.ny, self.dx, self.dy, self.dt = nx, ny, dx, dy, dt
+        self.npass, self.comp = npass, comp
+        self.ax, self.ay = np.arange(nx), np.arange(ny)
+
+    def gather(self, F, X, Y):
+        out = np.zeros(6)
+        for c, (sx, sy) in enumerate(STAGGER):
+            out[c] = _hat(Y - sy - self.ay, self.ny) @ F[c] @ _hat(X - sx - self.ax, self.nx)
+        return out
+
+    @staticmethod
+    def boris(qm, dt, f, u):
+        tau = 0.5 * dt * qm
+        um = u + tau * f[:3]
+        t = tau * f[3:] / math.sqrt(1.0 + um @ um)
+        up = um + np.cross(um, t)
+        s = 2.0 * t / (1.0 + t @ t)
+        return um + np.cross(up, s) + tau * f[:3]
+
+    def deposit(self, J, qp, X0, Y0, DX, DY, vz):
+        cuts = [0.0, 1.0]
+        for P, D in ((X0, DX), (Y0, DY)):
+            if D != 0.0:
+                for m in range(math.floor(min(P, P + D)), math.floor(max(P, P + D)) + 1):
+                    t = (m - P) / D
+                    if 0.0 < t < 1.0:
+                        cuts.append(t)
+        cuts.sort()
+
+        def nodes(X, Y):
+            return np.outer(_hat(Y - self.ay, self.ny), _hat(X - self.ax, self.nx))
+
+        for ta, tb in zip(cuts[:-1], cuts[1:]):
+            h, tm = tb - ta, 0.5 * (ta + tb)
+            Xm, Ym = X0 + tm * DX, Y0 + tm * DY
+            ci, cj = math.floor(Xm) % self.nx, math.floor(Ym) % self.ny
+            J[0][:, ci] += qp * h * DX * self.dx / self.dt * _hat(Ym - self.ay, self.ny)
+            J[1][cj, :] += qp * h * DY * self.dy / self.dt * _hat(Xm - self.ax, self.nx)
+            J[2] += qp * vz * h * (nodes(X0 + ta * DX, Y0 + ta * DY) + 4.0 * nodes(Xm, Ym)
+                                   + nodes(X0 + tb * DX, Y0 + tb * DY)) / 6.0
+
+    def filter(self, P):
+        for ax in (1, 0):
+            for _ in range(self.npass):
+                P = (np.roll(P, 1, ax) + 2.0 * P + np.roll(P, -1, ax)) / 4.0
+            if self.comp:
+                N = self.npass
+                P = (-N * np.roll(P, 1, ax) + (4.0 + 2 * N) * P - N * np.roll(P, -1, ax)) / 4.0
+        return P
+
+    def yee(self, F, J):
+        dx, dy, dt = self.dx, self.dy, self.dt
+        Ex, Ey, Ez, Bx, By, Bz = [F[c].copy() for c in range(6)]
+
+        def fwd(P, ax, h):   # (P[k+1] - P[k]) / h
+            return (np.roll(P, -1, ax) - P) / h
+
+        def bwd(P, ax, h):   # (P[k] - P[k-1]) / h
+            return (P - np.roll(P, 1, ax)) / h
+
+        def half_b():
+            nonlocal Bx, By, Bz
+            Bx = Bx - 0.5 * dt * fwd(Ez, 0, dy)
+            By = By + 0.5 * dt * fwd(Ez, 1, dx)
+            Bz = Bz - 0.5 * dt * (fwd(Ey, 1, dx) - fwd(Ex, 0, dy))
+
+        half_b()
+        Ex = Ex + dt * (bwd(Bz, 0, dy) - J[0])
+        Ey = Ey + dt * (-bwd(Bz, 1, dx) - J[1])
+        Ez = Ez + dt * (bwd(By, 1, dx) - bwd(Bx, 0, dy) - J[2])
+        half_b()
+        return np.array([Ex, Ey, Ez, Bx, By, Bz])
+
+    def step(self, F, species):
+        """species: list of (qm, qp, particle dict), particles updated in place.
+        Returns the new fields and the unfiltered and filtered current."""
+        J = np.zeros((3, self.ny, self.nx))
+        for qm, qp, p in species:
+            for q in range(len(p["ix"])):
+                X, Y = p["ix"][q] + p["x"][q], p["iy"][q] + p["y"][q]
+                u = self.boris(qm, self.dt, self.gather(F, X, Y),
+                               np.array([p["ux"][q], p["uy"][q], p["uz"][q]]))
+                g = math.sqrt(1.0 + u @ u)
+                DX, DY = self.dt * u[0] / (g * self.dx), self.dt * u[1] / (g * self.dy)
+                self.deposit(J, qp, X, Y, DX, DY, u[2] / g)
+                for key, cell, D, n in (("x", "ix", DX, self.nx), ("y", "iy", DY, self.ny)):
+                    w = p[key][q] + D
+                    d = math.floor(w)
+                    w -= d
+                    if w >= 1.0:
+                        w, d = w - 1.0, d + 1
+                    p[key][q], p[cell][q] = w, (p[cell][q] + d) % n
+                p["ux"][q], p["uy"][q], p["uz"][q] = u
+        Jf = np.array([self.filter(J[c]) for c in range(3)])
+        return self.yee(F, Jf), J, Jf
+
+    def energy(self, F, species):
+        area = self.dx * self.dy
+        ke = []
+        for qm, qp, p in species:
+            tau, mp, k = 0.5 * self.dt * qm, qp / qm, 0.0
+            for q in range(len(p["ix"])):
+                f = self.gather(F, p["ix"][q] + p["x"][q], p["iy"][q] + p["y"][q])
+                um = np.array([p["ux"][q], p["uy"][q], p["uz"][q]]) + tau * f[:3]
+                k += mp * (math.sqrt(1.0 + um @ um) - 1.0)
+            ke.append(k * area)
+        return 0.5 * (F[:3] ** 2).sum() * area, 0.5 * (F[3:] ** 2).sum() * area, ke
+
+
+@pytest.mark.parametrize("npass,comp", [(1, False), (1, True), (2, False)])
+def test_full_cycle_matches_naive_brute_force_on_a_tiny_box(npass, comp):
+    # 4 x 4 periodic box with non-square cells, two species of opposite sign,
+    # 32 particles fast enough to cross cells every few steps, random fields;
+    # 50 steps of the oracle against the naive cycle above
+    rng = np.random.default_rng(12)
+    nx, ny, dx, dy, dt = 4, 4, 0.1, 0.12, 0.07
+    s = OracleSim(nx, ny, nx * dx, ny * dy, dt, filter_passes=npass, filter_compensate=comp)
+    specs = [Species(-1.0, 1.0, ppc=(2, 1)), Species(0.5, 0.7, ppc=(1, 1))]
+    naive_sp = []
+    for sp in specs:
+        k = s.add_species(sp, load=False)
+        p = random_particles(rng, nx, ny, 16, uth=0.5)
+        s.set_particles(k, p)
+        qp = math.copysign(sp.density / (sp.ppc[0] * sp.ppc[1]), sp.qm)
+        assert s.qp(k) == qp
+        naive_sp.append((sp.qm, qp, {key: np.array(v, dtype=np.int64 if key in ("ix", "iy")
+                                                   else np.float64) for key, v in p.items()}))
+    F = 0.2 * rng.standard_normal((6, ny, nx))
+    s.set_fields(F)
+    nv = _NaivePIC(nx, ny, dx, dy, dt, npass, comp)
+    crossings = 0
+    for n in range(50):
+        before = [p["ix"] * 10 + p["iy"] for _, _, p in naive_sp]
+        s.step(1)
+        F, J, Jf = nv.step(F, naive_sp)
+        crossings += sum(int((b != p["ix"] * 10 + p["iy"]).sum())
+                         for b, (_, _, p) in zip(before, naive_sp))
+        for k, (_, _, p) in enumerate(naive_sp):
+            o = s.get_particles(k)
+            assert np.array_equal(o["ix"], p["ix"]) and np.array_equal(o["iy"], p["iy"]), n
+            for key in ("x", "y", "ux", "uy", "uz"):
+                assert np.abs(o[key] - p[key]).max() < 1e-12, (n, key)
+        scale_f = np.abs(F).max()
+        assert np.abs(s.get_fields() - F).max() < 1e-12 * scale_f, n
+        assert np.abs(s.get_current(filtered=False) - J).max() < 1e-12 * np.abs(J).max(), n
+        assert np.abs(s.get_current(filtered=True) - Jf).max() < 1e-12 * np.abs(Jf).max(), n
+        e = s.energy()
+        we, wb, ke = nv.energy(F, naive_sp)
+        assert abs(e["e_energy"] - we) < 1e-12 * we and abs(e["b_energy"] - wb) < 1e-12 * wb
+        assert np.allclose(e["ke"], ke, rtol=1e-12, atol=0)
+    # the run exercised the path splitting: many cell crossings in 50 steps
+    assert crossings > 100
+
+
+# ---------------------------------------------------------------------------
 # loading, laser, moving window (Sec. 4.1)
 # ---------------------------------------------------------------------------
 def test_loader_lattice_counts_and_moments():
