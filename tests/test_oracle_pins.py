@@ -339,6 +339,43 @@ def test_cold_plasma_frequency_from_zero_crossings():
     assert abs(2 * math.pi / period - 2 / dt * math.asin(dt / 2)) < 1e-4
 
 
+def _cold_mode_frequency(npass, comp, nx=64, steps=600, delta=1e-3, dt=0.07):
+    """Cold electrons on a 4 x 1 lattice per cell with u_x = delta sin(k x),
+    k the box's longest mode: the frequency of the Langmuir oscillation from
+    the zero crossings of E_x's projection on that mode."""
+    s = OracleSim(nx, 4, nx * 0.1, 0.4, dt, filter_passes=npass, filter_compensate=comp)
+    k = s.add_species(Species(-1.0, 1.0, ppc=(4, 1)))
+    p = s.get_particles(k)
+    kk = 2 * math.pi / (nx * 0.1)
+    p["ux"] = delta * np.sin(kk * (p["ix"] + p["x"]) * 0.1)
+    s.set_particles(k, p)
+    mode = np.sin(kk * (np.arange(nx) + 0.5) * 0.1)  # at the E_x points
+    a = []
+    for n in range(steps):
+        s.step(1)
+        f = s.get_fields()
+        assert np.abs(f[1:]).max() == 0.0  # purely longitudinal: only E_x
+        a.append(f[0].mean(axis=0) @ mode)
+    z = [n + a[n] / (a[n] - a[n + 1]) for n in range(steps - 1) if a[n] * a[n + 1] < 0]
+    return 2 * math.pi / (2 * (z[-1] - z[0]) / (len(z) - 1) * dt)
+
+
+def test_cold_plasma_finite_k_frequency_and_filter_gain():
+    # a finite-k cold Langmuir mode oscillates at the plasma frequency (grid and
+    # time-step corrections below 2e-3 at k dx = 2 pi / 64); filtering the
+    # current multiplies the restoring force by the filter's gain G(k), so for
+    # the leapfrog sin(w dt / 2) scales exactly by sqrt(G)
+    dt, kd = 0.07, 2 * math.pi / 64
+    w0 = _cold_mode_frequency(0, False)
+    assert abs(w0 - 1.0) < 2e-3
+    g, sn = math.cos(kd / 2) ** 2, math.sin(kd / 2) ** 2
+    for npass, comp, G in ((1, False, g), (2, False, g * g), (1, True, g * (1 + sn))):
+        w = _cold_mode_frequency(npass, comp)
+        assert abs(w - 1.0) < 3e-3
+        ratio = math.sin(w * dt / 2) / math.sin(w0 * dt / 2)
+        assert abs(ratio / math.sqrt(G) - 1) < 2e-6, (npass, comp)
+
+
 def test_gauss_law_and_continuity_every_step():
     # warm plasma with random initial fields whose div we subtract: for all n,
     # div E^n - div E^0 = F(rho^n - rho^0), F the filter
