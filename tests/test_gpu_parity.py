@@ -154,6 +154,52 @@ def test_one_step_matches_oracle(name):
     assert sim.status() == 0
 
 
+# empty and sparse particle sets: (workload, particles per species, fp64)
+SPARSE = {
+    "vacuum_40x36": (two_species(40, 36, 4.0, 3.6, filter_passes=1, filter_compensate=True),
+                     (0, 0), False),
+    "vacuum_window_60x20_fp64": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
+                                             filter_passes=1), (0, 0), True),
+    "one_species_empty_40x36": (two_species(40, 36, 4.0, 3.6, filter_passes=2), (0, 2880), False),
+    "seven_particles_40x36": (two_species(40, 36, 4.0, 3.6, filter_passes=1), (4, 3), False),
+    "three_particles_window_60x20": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
+                                                 filter_passes=1, filter_compensate=True),
+                                     (2, 1), False),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPARSE))
+def test_empty_and_sparse_particle_sets_match_oracle(name):
+    """One step with no particles at all (the field solver alone), with one
+    species empty, and with a handful of particles leaving almost every tile
+    empty; the window cases start one step before a shift."""
+    w, counts, fp64 = SPARSE[name]
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    parts = []
+    for s, n in zip(w.species, counts):
+        xr = (1, w.nx - 1) if w.moving_window else None
+        parts.append(round_to_f32(random_particles(rng, w.nx, w.ny, n, uth=0.4, ufl=s.ufl,
+                                                   x_range=xr)))
+    f = (0.2 * rng.standard_normal((6, w.ny, w.nx))).astype(np.float32).astype(np.float64)
+    it = int(math.ceil(3 * w.dx / w.dt)) - 1 if w.moving_window else 0
+    nsh = int(it * w.dt / w.dx + 1e-12) if w.moving_window else 0
+    sim, o = setup_pair(w, parts, f, fp64=fp64, it=it, nshift=nsh)
+    for k, n in enumerate(counts):
+        assert sim.count(k) == o.count(k) == n
+    step_both(sim, o, False)
+    if w.moving_window:
+        assert o.nshift == nsh + 1
+    compare_state(sim, o, w, fp64, name)
+    if sum(counts) == 0:
+        assert not sim.get_current(False).any()
+    # a few more steps on the GPU alone: the counts hold and nothing overflows
+    sim.step(5)
+    e = sim.energy()
+    assert e["status"] == 0 and sim.status() == 0
+    if not w.moving_window:
+        assert list(e["n_particles"]) == list(counts)
+
+
 @pytest.mark.parametrize("fp64", [False, True])
 def test_loader_matches_oracle(fp64):
     w = Workload("load", 40, 34, 4.0, 3.4, 0.07, 1,
