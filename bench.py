@@ -2,8 +2,8 @@
 """Benchmark of the 2D EM-PIC step on one MI355X.
 
 A step is one pass of the whole hot path over the resident simulation:
-interpolate + Boris push + charge-conserving deposit (k_push_deposit), tile
-hand-off (k_migrate), current fold, binomial filter, Yee field advance and the
+interpolate + Boris push + charge-conserving deposit + tile hand-off
+(k_push_deposit), current fold, binomial filter, Yee field advance and the
 step bookkeeping.  The default workload is the two counter-streaming electron
 clouds on a periodic 1024 x 1024 grid (16,777,216 particles, 16 per cell per
 species), whose particle arrays (0.4 GB read and written per step) are larger

@@ -382,11 +382,12 @@ template <typename R>
 int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
     int rc = PIC_OK;
-    if (!d.direct) {
+    if (!d.direct && !folds_in_yee(d)) {
         rc = timed(s, 2, st, [&] { return Launch<R>::fold(d, 3, d.J[0], d.J[1], d.J[2], st); });
         if (rc) return rc;
     }
-    // the Yee launch filters J itself (Jf is only written on request)
+    // the Yee launch filters J itself (Jf is only written on request), and
+    // folds it first where folds_in_yee
     rc = timed(s, 4, st, [&] { return Launch<R>::yee(d, st); });
     if (rc) return rc;
     if (d.window) {

@@ -240,6 +240,11 @@ hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, h
                              int rf = -1, int grid_fold = 0, int grid_yee = 0);
 
 // Launchers (defined in pic_kernels.hip for R = float and double).
+// The single-simulation step folds the current inside the Yee launch when
+// every tile has one float image (reduction deposit, one block per tile);
+// otherwise the fold runs as a launch of its own before it.
+template <typename R> inline bool folds_in_yee(const SimDev<R> &d) { return !d.direct && d.nsb == 1; }
+
 template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
     // only_if_shift: skip unless the last step shifted the moving window;
@@ -252,6 +257,7 @@ template <typename R> struct Launch {
     static hipError_t filter(const SimDev<R> &d, int nplanes, const R *i0, const R *i1,
                              const R *i2, R *o0, R *o1, R *o2, hipStream_t s,
                              bool before_shift = false);
+    // filter + Yee (+ the fold, where folds_in_yee) and the step's end
     static hipError_t yee(const SimDev<R> &d, hipStream_t s);
     static hipError_t window(const SimDev<R> &d, hipStream_t s);
     static hipError_t load(const SimDev<R> &d, int sp, hipStream_t s);

@@ -902,6 +902,64 @@ __global__ __launch_bounds__(64) void k_fold_sb(const SimDev<R> *__restrict__ ds
     fold_s_body<R, 1>(d, __builtin_amdgcn_readfirstlane(w.y), d.J[0], d.J[1], d.J[2]);
 }
 
+// Row a5 for a single cell (gx, gy) of the three current planes, from the
+// float tile images: the same images added in the same order as
+// fold_s_body (its fast path for a full-height tile at least 3 columns wide,
+// its general path otherwise), so the sums agree bit for bit.  The caller
+// clears gap columns.
+template <typename R>
+__device__ __forceinline__ void fold_cell(const SimDev<R> &d, int gx, int gy, R (&a)[3])
+{
+    const int tx = gx / TX, ty = gy / TY;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int lx = gx - x0, ly = gy - y0;
+    const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
+    const gptr<const R> blk = glob<const R>(d.blk);
+    auto img = [&](int ia, int ib) { return (size_t)(ia + ib * d.ntx) * 3 * BP; };
+    a[0] = a[1] = a[2] = R(0);
+    if (h == TY && w >= 3) {
+        const int txl = wrapi(tx - 1, d.ntx), txr = wrapi(tx + 1, d.ntx);
+        const int wl = min(TX, d.nxs - txl * TX);
+        const int xo = lx < 2 ? -1 : (lx == w - 1 ? 1 : 0);
+        const int txn = xo < 0 ? txl : (xo > 0 ? txr : tx);
+        const int cxo = lx + 1, cxn = xo < 0 ? lx + wl + 1 : (xo > 0 ? 0 : lx + 1);
+        // one level of images: the x neighbour first when it lies to the left
+        auto level = [&](int tyn, int row) {
+            const size_t io = img(tx, tyn) + cxo + row * PX, in = img(txn, tyn) + cxn + row * PX;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                // lanes without an x neighbour skip its load
+                const R o = blk[io + c * BP], n = xo != 0 ? blk[in + c * BP] : R(0);
+                a[c] += xo < 0 ? n : o;
+                a[c] += xo < 0 ? o : (xo > 0 ? n : R(0));
+            }
+        };
+        // the lower image reaches rows 0 and 1, the upper one row 15
+        if (ly < 2) {
+            const int tyl = wrapi(ty - 1, d.nty);
+            level(tyl, ly + min(TY, d.ny - tyl * TY) + 1);
+        }
+        level(ty, ly + 1);
+        if (ly == TY - 1) level(wrapi(ty + 1, d.nty), 0);
+        return;
+    }
+    for (int oy = -1; oy <= 1; ++oy) {
+        const int tyn = wrapi(ty + oy, d.nty);
+        const int hn = min(TY, d.ny - tyn * TY);
+        const int py = oy == 0 ? ly : (oy < 0 ? ly + hn : ly - h);
+        if (py < -1 || py >= hn + 2) continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+            const int txn = wrapi(tx + ox, d.ntx);
+            const int wn = min(TX, d.nxs - txn * TX);
+            const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
+            if (px < -1 || px >= wn + 2) continue;
+            const size_t b = img(txn, tyn) + (px + 1) + (py + 1) * PX;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[c] += blk[b + c * BP];
+        }
+    }
+}
+
 // Row a6 in streaming form, for the three current planes of one simulation
 // (the step runs the filter inside k_yee_s; this kernel serves requests for
 // the filtered current): each wavefront filters a strip of FS_S rows and
@@ -1007,7 +1065,7 @@ __global__ __launch_bounds__(64) void k_filter_s(SimDev<R> d, const R *i0, const
 // (B half at i - 1) and lanes beyond the strip (E at i + 1, i + 2): lanes
 // P .. 62 - P end with complete results.  The arithmetic is that of
 // filter_body and yee_body, term for term.
-template <typename R, int RF>
+template <typename R, int RF, bool FOLD = false>
 __device__ __forceinline__ void yee_s_body(const SimDev<R> &d, const int blk)
 {
     // no contraction into fma: the tile and streaming forms (and the batched
@@ -1044,11 +1102,31 @@ __device__ __forceinline__ void yee_s_body(const SimDev<R> &d, const int blk)
             if (q < YS_S + 2) bo[q][c] = glob<const R>(par ? d.F[1][3 + c] : d.F[0][3 + c])[g];
         }
     }
+    if constexpr (FOLD) {
+        // the current folded here from the tile images (fold_cell), and
+        // written to J on the strip's own cells, as the fold launch would
 #pragma unroll
-    for (int q = 0; q < NJ; ++q) {
-        const size_t g = at(r0 - RF + q);
+        for (int q = 0; q < NJ; ++q) {
+            int gy = (r0 - RF + q) % d.ny;
+            gy += gy < 0 ? d.ny : 0;
+            R v[3];
+            fold_cell(d, gx, gy, v);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ja[q][c] = glob<const R>(RF > 0 ? d.J[c] : d.Jf[c])[g];
+            for (int c = 0; c < 3; ++c) ja[q][c] = gp ? R(0) : v[c];
+            const int m = q - RF;
+            if (put && m >= 0 && m < nr) {
+                const size_t g = (size_t)gx + (size_t)gy * d.nxs;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) glob(d.J[c])[g] = ja[q][c];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            const size_t g = at(r0 - RF + q);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ja[q][c] = glob<const R>(RF > 0 ? d.J[c] : d.Jf[c])[g];
+        }
     }
     if constexpr (RF > 0) filter_rows<R, RF>(ja, gp, d.npass);
     R (&jj)[NJ][3] = ja;  // jj[RF + m]: row r0 + m
@@ -1106,6 +1184,14 @@ template <typename R, int RF>
 __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
 {
     yee_s_body<R, RF>(d, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// rows a5-a7 in one launch: the fold of the tile images as well (one block
+// per tile and float images, reduction deposit)
+template <typename R, int RF>
+__global__ __launch_bounds__(64) void k_fold_yee_s(SimDev<R> d)
+{
+    yee_s_body<R, RF, true>(d, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // the same over a batch whose simulations share the filter halo RF
@@ -1815,12 +1901,22 @@ hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
     const dim3 grid(yee_units(d.nxs, d.ny, rf));
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, d); };
     static_assert(MAX_FR == 4, "one instance per filter halo");
-    switch (rf) {
-    case 0: go(k_yee_s<R, 0>); break;
-    case 1: go(k_yee_s<R, 1>); break;
-    case 2: go(k_yee_s<R, 2>); break;
-    case 3: go(k_yee_s<R, 3>); break;
-    default: go(k_yee_s<R, 4>); break;
+    if (folds_in_yee(d)) {
+        switch (rf) {
+        case 0: go(k_fold_yee_s<R, 0>); break;
+        case 1: go(k_fold_yee_s<R, 1>); break;
+        case 2: go(k_fold_yee_s<R, 2>); break;
+        case 3: go(k_fold_yee_s<R, 3>); break;
+        default: go(k_fold_yee_s<R, 4>); break;
+        }
+    } else {
+        switch (rf) {
+        case 0: go(k_yee_s<R, 0>); break;
+        case 1: go(k_yee_s<R, 1>); break;
+        case 2: go(k_yee_s<R, 2>); break;
+        case 3: go(k_yee_s<R, 3>); break;
+        default: go(k_yee_s<R, 4>); break;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

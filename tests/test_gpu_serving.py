@@ -62,6 +62,10 @@ def test_batch_alone_equals_mixed_with_changing_membership():
     for sa, sm, w in zip(alone, mixed, ws):
         assert sm.energy()["step"] == sa.energy()["step"] == 30
         assert np.array_equal(sa.get_fields(), sm.get_fields()), w.name
+        # the last step's current: folded inside the Yee launch when stepped
+        # alone, by the separate fold launch in a batch of several (A and B)
+        assert np.array_equal(sa.get_current(False), sm.get_current(False)), w.name
+        assert np.array_equal(sa.get_current(True), sm.get_current(True)), w.name
         for k in range(len(w.species)):
             assert same_particles(sa.get_particles(k), sm.get_particles(k)), (w.name, k)
         assert sm.status() == 0
