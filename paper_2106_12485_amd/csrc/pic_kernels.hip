@@ -1901,14 +1901,11 @@ hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
     const dim3 grid(yee_units(d.nxs, d.ny, rf));
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, d); };
     static_assert(MAX_FR == 4, "one instance per filter halo");
-    if (folds_in_yee(d)) {
-        switch (rf) {
-        case 0: go(k_fold_yee_s<R, 0>); break;
-        case 1: go(k_fold_yee_s<R, 1>); break;
-        case 2: go(k_fold_yee_s<R, 2>); break;
-        case 3: go(k_fold_yee_s<R, 3>); break;
-        default: go(k_fold_yee_s<R, 4>); break;
-        }
+    if (folds_in_yee(d)) {  // filter halo 0 or 1
+        if (rf == 0)
+            go(k_fold_yee_s<R, 0>);
+        else
+            go(k_fold_yee_s<R, 1>);
     } else {
         switch (rf) {
         case 0: go(k_yee_s<R, 0>); break;
