@@ -237,10 +237,12 @@ int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream);
  * not from the graph).  pic_timing(sim, 1) resets and starts, 0 stops.
  * pic_timing_read fills ms[k] (summed milliseconds) and launches[k] for
  * k < nk of: 0 push + deposit (its last block flips the particle buffers),
- * 1 hand-off of pending leavers (settle), 2 fold, 3 filter (only the
- * requests of pic_get_current: the step filters inside the Yee launch),
- * 4 current filter + Yee and the step end (field buffer flip, step count),
- * 5 moving-window shift.
+ * 1 hand-off of pending leavers (settle), 2 fold (a launch of its own only
+ * for filter halos of 2 or more, per-species push blocks or batches; else
+ * the Yee launch folds), 3 filter (only the requests of pic_get_current:
+ * the step filters inside the Yee launch), 4 current filter + Yee (and the
+ * fold, where it has no launch of its own) and the step end (field buffer
+ * flip, step count), 5 moving-window shift.
  * Synchronises. */
 #define PIC_NK 6
 int pic_timing(pic_sim *sim, int enable, void *stream);
