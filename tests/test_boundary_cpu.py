@@ -73,6 +73,12 @@ def test_validation_rejects_bad_configurations(libpic):
 
     assert "Courant" in bad(dt=0.1 / math.sqrt(2) * 1.0001)
     assert "nx" in bad(nx=1)
+    # cell indices are packed in 16 bits each: 32767 is the largest extent
+    assert "32767" in bad(nx=32768, lx=3276.8)
+    assert "32767" in bad(ny=32768, ly=3276.8)
+    c = pic.make_cfg(w)
+    c.nx, c.lx, c.ny, c.ly = 32767, 3276.7, 32767, 3276.7
+    assert libpic.pic_mem_bytes(C.byref(c)) > 0
     assert "16" in bad(nx=33)
     assert "n_species" in bad(n_species=5)
     assert "filter" in bad(filter_passes=0, filter_compensate=1)

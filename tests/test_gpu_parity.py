@@ -98,7 +98,7 @@ CASES = {
     # three strips of columns (the last one ragged) and five of rows; halo 3
     "two_passes_comp_130x40": (two_species(130, 40, 13.0, 4.0, filter_passes=2,
                                            filter_compensate=True), False, False),
-    # odd sizes against the streaming strips (61/59/57/55 columns by 8 rows for
+    # odd sizes against the streaming strips (61/59/57/55 columns by 6 rows for
     # filter + Yee, 4-tile rows for the fold): ragged strips on both axes
     "odd_67x9": (two_species(67, 9, 6.7, 0.9, filter_passes=1), False, False),
     "odd_66x66_three": (two_species(66, 66, 6.6, 6.6, filter_passes=3), False, False),
@@ -165,14 +165,22 @@ SPARSE = {
     "three_particles_window_60x20": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
                                                  filter_passes=1, filter_compensate=True),
                                      (2, 1), False),
+    # the largest grid extents (32767 cells: cell indices use 16 bits each,
+    # ragged last tile of 15), a few hundred particles
+    "max_nx_32767x18": (two_species(32767, 18, 3276.7, 1.8, filter_passes=1), (300, 200), False),
+    "max_ny_18x32767": (two_species(18, 32767, 1.8, 3276.7, filter_passes=1,
+                                    filter_compensate=True), (300, 200), False),
+    "max_nx_window_32767x18": (two_species(32767, 18, 655.34, 3.6, dt=0.014, moving_window=True,
+                                           filter_passes=1), (300, 200), False),
 }
 
 
 @pytest.mark.parametrize("name", sorted(SPARSE))
 def test_empty_and_sparse_particle_sets_match_oracle(name):
     """One step with no particles at all (the field solver alone), with one
-    species empty, and with a handful of particles leaving almost every tile
-    empty; the window cases start one step before a shift."""
+    species empty, with a handful of particles leaving almost every tile
+    empty, and on the largest grid extents; the window cases start one step
+    before a shift."""
     w, counts, fp64 = SPARSE[name]
     rng = np.random.default_rng(zlib.crc32(name.encode()))
     parts = []
