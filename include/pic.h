@@ -183,8 +183,9 @@ int pic_field_advance(pic_sim *sim, void *stream);
 
 /* nsteps times (pic_deposit; pic_field_advance).  Between steps the leavers
  * of a push stay in their outboxes and the next push takes them from there
- * (calls that read particles append them first).  After the first call the
- * step is replayed from a captured HIP graph.  Asynchronous on stream. */
+ * (calls that read particles append them first).  The steps are replayed
+ * from HIP graphs captured on first use: one of 8 steps while 8 or more
+ * remain, then one of a single step.  Asynchronous on stream. */
 int pic_step(pic_sim *sim, int nsteps, void *stream);
 
 /* FP64 diagnostics of the current state (see pic_diag).  Synchronises. */

@@ -1,7 +1,7 @@
 // Host side of libpic: the C ABI declared in include/pic.h.  Validates the
 // configuration, lays the simulation out in the caller's device arena, moves
 // host state in and out, and enqueues the kernels of pic_kernels.hip on the
-// caller's stream (directly, or from a captured one-step HIP graph).
+// caller's stream (directly, or from captured HIP graphs of one or eight steps).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -280,8 +280,10 @@ struct pic_sim {
     SimDev<float> df;
     SimDev<double> dd;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec = nullptr;   // one step
     hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec_n = nullptr; // GRAPH_STEPS steps
+    hipGraph_t graph_n = nullptr;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -665,6 +667,31 @@ int do_planes(pic_sim *s, R *const *dev, int np, double *host, bool to_dev, hipS
     return PIC_OK;
 }
 
+// Steps replayed from captured graphs: one of GRAPH_STEPS steps while that
+// many remain, then one-step graphs (fewer graph launches, and no gap
+// between the steps inside one graph).
+constexpr int GRAPH_STEPS = 8;
+
+template <typename R>
+int capture_steps(pic_sim *s, const SimDev<R> &d, int k, hipGraph_t *graph, hipGraphExec_t *exec)
+{
+    if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+    int rc = PIC_OK;
+    for (int n = 0; n < k && rc == PIC_OK; ++n) rc = enqueue_step(s, d, s->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return fail(PIC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    *graph = g;
+    HIPCHK(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+    return PIC_OK;
+}
+
 template <typename R>
 int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
 {
@@ -675,19 +702,16 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
         }
         return PIC_OK;
     }
-    if (!s->gexec) {
-        if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-        HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-        int rc = enqueue_step(s, d, s->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (nsteps >= GRAPH_STEPS && !s->gexec_n) {
+        const int rc = capture_steps(s, d, GRAPH_STEPS, &s->graph_n, &s->gexec_n);
         if (rc) return rc;
-        if (e != hipSuccess)
-            return fail(PIC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        s->graph = g;
-        HIPCHK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
     }
-    for (int n = 0; n < nsteps; ++n) HIPCHK(hipGraphLaunch(s->gexec, st));
+    if (nsteps % GRAPH_STEPS && !s->gexec) {
+        const int rc = capture_steps(s, d, 1, &s->graph, &s->gexec);
+        if (rc) return rc;
+    }
+    for (int n = 0; n < nsteps / GRAPH_STEPS; ++n) HIPCHK(hipGraphLaunch(s->gexec_n, st));
+    for (int n = 0; n < nsteps % GRAPH_STEPS; ++n) HIPCHK(hipGraphLaunch(s->gexec, st));
     return PIC_OK;
 }
 
@@ -799,6 +823,8 @@ int pic_free(pic_sim *sim)
     if (!sim) return PIC_OK;
     if (sim->gexec) (void)hipGraphExecDestroy(sim->gexec);
     if (sim->graph) (void)hipGraphDestroy(sim->graph);
+    if (sim->gexec_n) (void)hipGraphExecDestroy(sim->gexec_n);
+    if (sim->graph_n) (void)hipGraphDestroy(sim->graph_n);
     if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
     for (hipEvent_t e : sim->ev) (void)hipEventDestroy(e);
     delete sim;
