@@ -69,8 +69,8 @@ struct DevState {
 // opar (if pending), and writes the particles that stay, compacted, to buffer
 // ppar ^ 1 and the ones that leave to outbox opar ^ 1, each tagged with the
 // direction (dx, dy) of its tile step; the neighbour in that direction picks
-// it up.  k_push_end then flips both parities and marks the new outbox
-// pending; k_settle appends pending leavers to their tiles when the particle
+// it up.  The launch's last block to finish then flips both parities and
+// marks the new outbox pending; k_settle appends pending leavers to their tiles when the particle
 // set must be complete (host reads, diagnostics, window shifts).
 constexpr int N_DIR = 8;
 __device__ __forceinline__ int dir_index(int dtx, int dty)

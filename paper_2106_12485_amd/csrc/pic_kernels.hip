@@ -961,8 +961,8 @@ __device__ __forceinline__ void fold_cell(const SimDev<R> &d, int gx, int gy, R 
 }
 
 // Row a6 in streaming form, for the three current planes of one simulation
-// (the step runs the filter inside k_yee_s; this kernel serves requests for
-// the filtered current): each wavefront filters a strip of FS_S rows and
+// (the step runs the filter inside its Yee launch, k_fold_yee_s or k_yee_s;
+// this kernel serves requests for the filtered current): each wavefront filters a strip of FS_S rows and
 // 64 - 2 RF columns, where RF = npass + compensate.  Lane L holds column
 // c0 + L - RF of every row.  The x passes take their neighbours from the
 // adjacent lanes, the y passes from the rows held in registers.  The
