@@ -9,10 +9,14 @@
 #include <chrono>
 #include <cmath>
 #include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
 #include <thread>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pic.h"
@@ -28,6 +32,28 @@ int fail(int code, const std::string &msg)
 {
     g_err = msg;
     return code;
+}
+
+// No C++ exception crosses the ABI: a failed host allocation (or a request
+// for more than a vector can hold) becomes PIC_E_NOMEM, anything else
+// PIC_E_STATE, with the message in pic_last_error.  Entry points returning a
+// status (int, long long) return that code; those returning a size return 0.
+template <typename T, typename F>
+T guarded(F &&body) noexcept
+{
+    int code = PIC_E_STATE;
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        code = fail(PIC_E_NOMEM, "host memory allocation failed");
+    } catch (const std::length_error &) {
+        code = fail(PIC_E_NOMEM, "host buffer larger than a vector can hold");
+    } catch (const std::exception &e) {
+        code = fail(PIC_E_STATE, std::string("C++ exception: ") + e.what());
+    } catch (...) {
+        code = fail(PIC_E_STATE, "unknown C++ exception");
+    }
+    return std::is_signed<T>::value ? (T)code : T(0);
 }
 
 #define HIPCHK(call)                                                                     \
@@ -738,84 +764,97 @@ extern "C" {
 
 size_t pic_mem_bytes(const pic_cfg *cfg)
 {
-    Layout L;
-    if (layout(cfg, &L) != PIC_OK) return 0;
-    return L.total;
+    return guarded<size_t>([&]() -> size_t {
+        Layout L;
+        if (layout(cfg, &L) != PIC_OK) return 0;
+        return L.total;
+    });
 }
 
 int pic_init(const pic_cfg *cfg, void *arena, size_t arena_bytes, void *stream, pic_sim **out)
 {
-    if (!out) return fail(PIC_E_ARG, "out is NULL");
-    *out = nullptr;
-    Layout L;
-    int rc = layout(cfg, &L);
-    if (rc) return rc;
-    if (!arena) return fail(PIC_E_ARG, "arena is NULL");
-    if (((uintptr_t)arena) & 255) return fail(PIC_E_ARG, "arena must be 256-byte aligned");
-    if (arena_bytes < L.total)
-        return fail(PIC_E_NOMEM, "arena holds " + std::to_string(arena_bytes) + " bytes, needs " +
-                                     std::to_string(L.total));
-    pic_sim *s = new pic_sim();
-    s->uid = g_next_uid.fetch_add(1);
-    s->cfg = *cfg;
-    s->L = L;
-    s->arena = (char *)arena;
-    std::memset(s->ms, 0, sizeof(s->ms));
-    std::memset(s->launches, 0, sizeof(s->launches));
-    hipStream_t st = (hipStream_t)stream;
-    if (cfg->fp64) {
-        describe(cfg, L, s->arena, &s->dd);
-        rc = do_init(s, s->dd, st);
-    } else {
-        describe(cfg, L, s->arena, &s->df);
-        rc = do_init(s, s->df, st);
-    }
-    if (rc) {
-        pic_free(s);
-        return rc;
-    }
-    *out = s;
-    return PIC_OK;
+    return guarded<int>([&]() -> int {
+        if (!out) return fail(PIC_E_ARG, "out is NULL");
+        *out = nullptr;
+        Layout L;
+        int rc = layout(cfg, &L);
+        if (rc) return rc;
+        if (!arena) return fail(PIC_E_ARG, "arena is NULL");
+        if (((uintptr_t)arena) & 255) return fail(PIC_E_ARG, "arena must be 256-byte aligned");
+        if (arena_bytes < L.total)
+            return fail(PIC_E_NOMEM, "arena holds " + std::to_string(arena_bytes) + " bytes, needs " +
+                                         std::to_string(L.total));
+        // released to the caller on success; pic_free on any failure, thrown or returned
+        std::unique_ptr<pic_sim, int (*)(pic_sim *)> own(new pic_sim(), pic_free);
+        pic_sim *s = own.get();
+        s->uid = g_next_uid.fetch_add(1);
+        s->cfg = *cfg;
+        s->L = L;
+        s->arena = (char *)arena;
+        std::memset(s->ms, 0, sizeof(s->ms));
+        std::memset(s->launches, 0, sizeof(s->launches));
+        hipStream_t st = (hipStream_t)stream;
+        if (cfg->fp64) {
+            describe(cfg, L, s->arena, &s->dd);
+            rc = do_init(s, s->dd, st);
+        } else {
+            describe(cfg, L, s->arena, &s->df);
+            rc = do_init(s, s->df, st);
+        }
+        if (rc) return rc;
+        *out = own.release();
+        return PIC_OK;
+    });
 }
 
 int pic_deposit(pic_sim *sim, void *stream)
 {
-    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim, enqueue_deposit(sim, sim->df, st), enqueue_deposit(sim, sim->dd, st));
+    return guarded<int>([&]() -> int {
+        if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim, enqueue_deposit(sim, sim->df, st), enqueue_deposit(sim, sim->dd, st));
+    });
 }
 
 int pic_field_advance(pic_sim *sim, void *stream)
 {
-    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim, enqueue_field_advance(sim, sim->df, st),
-                    enqueue_field_advance(sim, sim->dd, st));
+    return guarded<int>([&]() -> int {
+        if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim, enqueue_field_advance(sim, sim->df, st),
+                        enqueue_field_advance(sim, sim->dd, st));
+    });
 }
 
 int pic_step(pic_sim *sim, int nsteps, void *stream)
 {
-    if (!sim || nsteps < 0) return fail(PIC_E_ARG, "bad sim or nsteps");
-    if (nsteps == 0) return PIC_OK;
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim, do_step(sim, sim->df, nsteps, st), do_step(sim, sim->dd, nsteps, st));
+    return guarded<int>([&]() -> int {
+        if (!sim || nsteps < 0) return fail(PIC_E_ARG, "bad sim or nsteps");
+        if (nsteps == 0) return PIC_OK;
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim, do_step(sim, sim->df, nsteps, st), do_step(sim, sim->dd, nsteps, st));
+    });
 }
 
 int pic_energy(pic_sim *sim, pic_diag *out, void *stream)
 {
-    if (!sim || !out) return fail(PIC_E_ARG, "sim or out is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim, do_energy(sim, sim->df, out, st), do_energy(sim, sim->dd, out, st));
+    return guarded<int>([&]() -> int {
+        if (!sim || !out) return fail(PIC_E_ARG, "sim or out is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim, do_energy(sim, sim->df, out, st), do_energy(sim, sim->dd, out, st));
+    });
 }
 
 int pic_status(pic_sim *sim, void *stream)
 {
-    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
-    int rc = read_state(sim, (hipStream_t)stream);
-    if (rc) return rc;
-    if (sim->hs.err & ERR_CAPACITY)
-        return fail(PIC_E_CAPACITY, "a tile or outbox ran out of particle slots");
-    return PIC_OK;
+    return guarded<int>([&]() -> int {
+        if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+        int rc = read_state(sim, (hipStream_t)stream);
+        if (rc) return rc;
+        if (sim->hs.err & ERR_CAPACITY)
+            return fail(PIC_E_CAPACITY, "a tile or outbox ran out of particle slots");
+        return PIC_OK;
+    });
 }
 
 int pic_free(pic_sim *sim)
@@ -835,122 +874,144 @@ int pic_set_particles(pic_sim *sim, int sp, long long n, const int *ix, const in
                       const double *x, const double *y, const double *ux, const double *uy,
                       const double *uz, void *stream)
 {
-    if (!sim || sp < 0 || sp >= sim->cfg.n_species || n < 0)
-        return fail(PIC_E_ARG, "bad sim, species or count");
-    if (n > 0 && (!ix || !iy || !x || !y || !ux || !uy || !uz))
-        return fail(PIC_E_ARG, "NULL particle array");
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim,
-                    do_set_particles(sim, sim->df, sp, n, ix, iy, x, y, ux, uy, uz, st),
-                    do_set_particles(sim, sim->dd, sp, n, ix, iy, x, y, ux, uy, uz, st));
+    return guarded<int>([&]() -> int {
+        if (!sim || sp < 0 || sp >= sim->cfg.n_species || n < 0)
+            return fail(PIC_E_ARG, "bad sim, species or count");
+        if (n > 0 && (!ix || !iy || !x || !y || !ux || !uy || !uz))
+            return fail(PIC_E_ARG, "NULL particle array");
+        if (n > (long long)sim->L.ntiles * sim->L.cap[sp])
+            return fail(PIC_E_CAPACITY, "more particles than the species has slots");
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim,
+                        do_set_particles(sim, sim->df, sp, n, ix, iy, x, y, ux, uy, uz, st),
+                        do_set_particles(sim, sim->dd, sp, n, ix, iy, x, y, ux, uy, uz, st));
+    });
 }
 
 long long pic_particle_count(pic_sim *sim, int sp, void *stream)
 {
-    if (!sim || sp < 0 || sp >= sim->cfg.n_species) return fail(PIC_E_ARG, "bad sim or species");
-    long long n = 0;
-    hipStream_t st = (hipStream_t)stream;
-    int rc = DISPATCH(sim,
-                      do_get_particles(sim, sim->df, sp, 0, &n, nullptr, nullptr, nullptr,
-                                       nullptr, nullptr, nullptr, nullptr, st),
-                      do_get_particles(sim, sim->dd, sp, 0, &n, nullptr, nullptr, nullptr,
-                                       nullptr, nullptr, nullptr, nullptr, st));
-    return rc ? rc : n;
+    return guarded<long long>([&]() -> long long {
+        if (!sim || sp < 0 || sp >= sim->cfg.n_species) return fail(PIC_E_ARG, "bad sim or species");
+        long long n = 0;
+        hipStream_t st = (hipStream_t)stream;
+        int rc = DISPATCH(sim,
+                          do_get_particles(sim, sim->df, sp, 0, &n, nullptr, nullptr, nullptr,
+                                           nullptr, nullptr, nullptr, nullptr, st),
+                          do_get_particles(sim, sim->dd, sp, 0, &n, nullptr, nullptr, nullptr,
+                                           nullptr, nullptr, nullptr, nullptr, st));
+        return rc ? rc : n;
+    });
 }
 
 int pic_get_particles(pic_sim *sim, int sp, long long cap, long long *n_out, int *ix, int *iy,
                       double *x, double *y, double *ux, double *uy, double *uz, void *stream)
 {
-    if (!sim || sp < 0 || sp >= sim->cfg.n_species || !ix || !iy || !x || !y || !ux || !uy ||
-        !uz)
-        return fail(PIC_E_ARG, "bad sim, species or NULL array");
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim,
-                    do_get_particles(sim, sim->df, sp, cap, n_out, ix, iy, x, y, ux, uy, uz, st),
-                    do_get_particles(sim, sim->dd, sp, cap, n_out, ix, iy, x, y, ux, uy, uz, st));
+    return guarded<int>([&]() -> int {
+        if (!sim || sp < 0 || sp >= sim->cfg.n_species || !ix || !iy || !x || !y || !ux || !uy ||
+            !uz)
+            return fail(PIC_E_ARG, "bad sim, species or NULL array");
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim,
+                        do_get_particles(sim, sim->df, sp, cap, n_out, ix, iy, x, y, ux, uy, uz, st),
+                        do_get_particles(sim, sim->dd, sp, cap, n_out, ix, iy, x, y, ux, uy, uz, st));
+    });
 }
 
 int pic_set_fields(pic_sim *sim, const double *f6, void *stream)
 {
-    if (!sim || !f6) return fail(PIC_E_ARG, "bad sim or NULL planes");
-    hipStream_t st = (hipStream_t)stream;
-    int rc = read_state(sim, st);
-    if (rc) return rc;
-    const int par = sim->hs.parity;
-    if (sim->cfg.fp64) {
-        rc = do_planes(sim, sim->dd.F[par], 6, (double *)f6, true, st);
-        if (!rc) rc = gauss_baseline(sim, sim->dd, st);
-    } else {
-        rc = do_planes(sim, sim->df.F[par], 6, (double *)f6, true, st);
-        if (!rc) rc = gauss_baseline(sim, sim->df, st);
-    }
-    return rc;
+    return guarded<int>([&]() -> int {
+        if (!sim || !f6) return fail(PIC_E_ARG, "bad sim or NULL planes");
+        hipStream_t st = (hipStream_t)stream;
+        int rc = read_state(sim, st);
+        if (rc) return rc;
+        const int par = sim->hs.parity;
+        if (sim->cfg.fp64) {
+            rc = do_planes(sim, sim->dd.F[par], 6, (double *)f6, true, st);
+            if (!rc) rc = gauss_baseline(sim, sim->dd, st);
+        } else {
+            rc = do_planes(sim, sim->df.F[par], 6, (double *)f6, true, st);
+            if (!rc) rc = gauss_baseline(sim, sim->df, st);
+        }
+        return rc;
+    });
 }
 
 int pic_get_fields(pic_sim *sim, double *f6, void *stream)
 {
-    if (!sim || !f6) return fail(PIC_E_ARG, "bad sim or NULL planes");
-    hipStream_t st = (hipStream_t)stream;
-    int rc = read_state(sim, st);
-    if (rc) return rc;
-    const int par = sim->hs.parity;
-    return DISPATCH(sim, do_planes(sim, sim->df.F[par], 6, f6, false, st),
-                    do_planes(sim, sim->dd.F[par], 6, f6, false, st));
+    return guarded<int>([&]() -> int {
+        if (!sim || !f6) return fail(PIC_E_ARG, "bad sim or NULL planes");
+        hipStream_t st = (hipStream_t)stream;
+        int rc = read_state(sim, st);
+        if (rc) return rc;
+        const int par = sim->hs.parity;
+        return DISPATCH(sim, do_planes(sim, sim->df.F[par], 6, f6, false, st),
+                        do_planes(sim, sim->dd.F[par], 6, f6, false, st));
+    });
 }
 
 int pic_get_current(pic_sim *sim, int filtered, double *j3, void *stream)
 {
-    if (!sim || !j3) return fail(PIC_E_ARG, "bad sim or NULL planes");
-    hipStream_t st = (hipStream_t)stream;
-    return DISPATCH(sim, get_current(sim, sim->df, filtered, j3, st),
-                    get_current(sim, sim->dd, filtered, j3, st));
+    return guarded<int>([&]() -> int {
+        if (!sim || !j3) return fail(PIC_E_ARG, "bad sim or NULL planes");
+        hipStream_t st = (hipStream_t)stream;
+        return DISPATCH(sim, get_current(sim, sim->df, filtered, j3, st),
+                        get_current(sim, sim->dd, filtered, j3, st));
+    });
 }
 
 int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream)
 {
-    if (!sim || iter < 0 || nshift < 0) return fail(PIC_E_ARG, "bad sim, iter or nshift");
-    hipStream_t st = (hipStream_t)stream;
-    int rc = read_state(sim, st);
-    if (rc) return rc;
-    sim->hs.iter = iter;
-    sim->hs.nshift = nshift;
-    sim->rho_prev_iter = -2;
-    return write_state(sim, st);
+    return guarded<int>([&]() -> int {
+        if (!sim || iter < 0 || nshift < 0) return fail(PIC_E_ARG, "bad sim, iter or nshift");
+        hipStream_t st = (hipStream_t)stream;
+        int rc = read_state(sim, st);
+        if (rc) return rc;
+        sim->hs.iter = iter;
+        sim->hs.nshift = nshift;
+        sim->rho_prev_iter = -2;
+        return write_state(sim, st);
+    });
 }
 
 int pic_timing(pic_sim *sim, int enable, void *stream)
 {
-    if (!sim) return fail(PIC_E_ARG, "sim is NULL");
-    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-    sim->timing = enable != 0;
-    sim->ev_used = 0;
-    if (enable) {
-        std::memset(sim->ms, 0, sizeof(sim->ms));
-        std::memset(sim->launches, 0, sizeof(sim->launches));
-    }
-    return PIC_OK;
+    return guarded<int>([&]() -> int {
+        if (!sim) return fail(PIC_E_ARG, "sim is NULL");
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+        sim->timing = enable != 0;
+        sim->ev_used = 0;
+        if (enable) {
+            std::memset(sim->ms, 0, sizeof(sim->ms));
+            std::memset(sim->launches, 0, sizeof(sim->launches));
+        }
+        return PIC_OK;
+    });
 }
 
 int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void *stream)
 {
-    if (!sim || nk < 0) return fail(PIC_E_ARG, "bad sim or nk");
-    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-    int rc = timing_flush(sim);
-    if (rc) return rc;
-    for (int k = 0; k < nk && k < PIC_NK; ++k) {
-        if (ms) ms[k] = sim->ms[k];
-        if (launches) launches[k] = sim->launches[k];
-    }
-    return PIC_OK;
+    return guarded<int>([&]() -> int {
+        if (!sim || nk < 0) return fail(PIC_E_ARG, "bad sim or nk");
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+        int rc = timing_flush(sim);
+        if (rc) return rc;
+        for (int k = 0; k < nk && k < PIC_NK; ++k) {
+            if (ms) ms[k] = sim->ms[k];
+            if (launches) launches[k] = sim->launches[k];
+        }
+        return PIC_OK;
+    });
 }
 
 int pic_layout(const pic_sim *sim, long long *out, int n)
 {
-    if (!sim || !out) return fail(PIC_E_ARG, "bad sim or out");
-    const long long v[7] = {TX, TY, sim->L.ntx, sim->L.nty, sim->L.nxs,
-                            sim->cfg.n_species ? sim->L.cap[0] : 0, sim->L.cap_out};
-    for (int k = 0; k < n && k < 7; ++k) out[k] = v[k];
-    return PIC_OK;
+    return guarded<int>([&]() -> int {
+        if (!sim || !out) return fail(PIC_E_ARG, "bad sim or out");
+        const long long v[7] = {TX, TY, sim->L.ntx, sim->L.nty, sim->L.nxs,
+                                sim->cfg.n_species ? sim->L.cap[0] : 0, sim->L.cap_out};
+        for (int k = 0; k < n && k < 7; ++k) out[k] = v[k];
+        return PIC_OK;
+    });
 }
 
 const char *pic_strerror(int code)
@@ -1026,10 +1087,12 @@ extern "C" {
 
 size_t pic_batch_mem_bytes(int max_sims, long long max_tiles)
 {
-    if (max_sims < 1 || max_tiles < 1) return 0;
-    size_t a, b, c, f, y, t;
-    batch_layout(max_sims, max_tiles, &a, &b, &c, &f, &y, &t);
-    return t;
+    return guarded<size_t>([&]() -> size_t {
+        if (max_sims < 1 || max_tiles < 1) return 0;
+        size_t a, b, c, f, y, t;
+        batch_layout(max_sims, max_tiles, &a, &b, &c, &f, &y, &t);
+        return t;
+    });
 }
 
 int pic_batch_free(pic_batch *b)
@@ -1050,129 +1113,133 @@ int pic_batch_free(pic_batch *b)
 int pic_batch_create(void *arena, size_t arena_bytes, int max_sims, long long max_tiles,
                      pic_batch **out)
 {
-    if (!out) return fail(PIC_E_ARG, "out is NULL");
-    *out = nullptr;
-    if (!arena || ((uintptr_t)arena & 255) || max_sims < 1 || max_tiles < 1)
-        return fail(PIC_E_ARG, "bad batch arena or sizes");
-    size_t ot, ob, ow, of, oy, total;
-    batch_layout(max_sims, max_tiles, &ot, &ob, &ow, &of, &oy, &total);
-    if (arena_bytes < total) return fail(PIC_E_NOMEM, "batch arena too small");
-    pic_batch *b = new pic_batch();
-    b->arena = (char *)arena;
-    b->max_sims = max_sims;
-    b->max_tiles = max_tiles;
-    b->d_table = (SimDev<float> *)(b->arena + ot);
-    b->d_batch = (BatchDev *)(b->arena + ob);
-    b->d_work = (int2 *)(b->arena + ow);
-    b->d_fwork = (int2 *)(b->arena + of);
-    b->d_ywork = (int2 *)(b->arena + oy);
-    hipError_t e = hipHostMalloc((void **)&b->h_table, (size_t)max_sims * sizeof(SimDev<float>));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_batch, sizeof(BatchDev));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_work, (size_t)max_tiles * sizeof(int2));
-    const size_t su = (size_t)max_tiles * SUNITS_PER_TILE * sizeof(int2);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_fwork, su);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_ywork, su);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        pic_batch_free(b);
-        return fail(PIC_E_HIP, std::string("batch set-up: ") + hipGetErrorString(e));
-    }
-    *out = b;
-    return PIC_OK;
+    return guarded<int>([&]() -> int {
+        if (!out) return fail(PIC_E_ARG, "out is NULL");
+        *out = nullptr;
+        if (!arena || ((uintptr_t)arena & 255) || max_sims < 1 || max_tiles < 1)
+            return fail(PIC_E_ARG, "bad batch arena or sizes");
+        size_t ot, ob, ow, of, oy, total;
+        batch_layout(max_sims, max_tiles, &ot, &ob, &ow, &of, &oy, &total);
+        if (arena_bytes < total) return fail(PIC_E_NOMEM, "batch arena too small");
+        pic_batch *b = new pic_batch();
+        b->arena = (char *)arena;
+        b->max_sims = max_sims;
+        b->max_tiles = max_tiles;
+        b->d_table = (SimDev<float> *)(b->arena + ot);
+        b->d_batch = (BatchDev *)(b->arena + ob);
+        b->d_work = (int2 *)(b->arena + ow);
+        b->d_fwork = (int2 *)(b->arena + of);
+        b->d_ywork = (int2 *)(b->arena + oy);
+        hipError_t e = hipHostMalloc((void **)&b->h_table, (size_t)max_sims * sizeof(SimDev<float>));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_batch, sizeof(BatchDev));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_work, (size_t)max_tiles * sizeof(int2));
+        const size_t su = (size_t)max_tiles * SUNITS_PER_TILE * sizeof(int2);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_fwork, su);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_ywork, su);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            pic_batch_free(b);
+            return fail(PIC_E_HIP, std::string("batch set-up: ") + hipGetErrorString(e));
+        }
+        *out = b;
+        return PIC_OK;
+    });
 }
 
 int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *stream)
 {
-    if (!b || n < 0 || nsteps < 0 || (n > 0 && !sims)) return fail(PIC_E_ARG, "bad batch call");
-    if (n == 0 || nsteps == 0) return PIC_OK;
-    if (n > b->max_sims) return fail(PIC_E_ARG, "more simulations than the batch holds");
-    hipStream_t st = (hipStream_t)stream;
-    bool same = (int)b->cur.size() == n;
-    for (int i = 0; same && i < n; ++i) same = sims[i] && sims[i]->uid == b->cur[i];
-    if (!same) {
-        long long nwork = 0;
-        for (int i = 0; i < n; ++i) {
-            const pic_sim *s = sims[i];
-            if (!s || s->cfg.fp64 || s->cfg.moving_window || s->cfg.deposit_mode != 0)
-                return fail(PIC_E_ARG, "batches hold FP32 periodic simulations with the "
-                                       "reduction deposit only");
-            nwork += s->L.ntiles;
-        }
-        if (nwork > b->max_tiles) return fail(PIC_E_ARG, "batch work list too long");
-        // the streaming field kernels need one filter halo for the whole batch
-        int rf = -1;
-        for (int i = 0; i < n; ++i) {
-            const pic_cfg &c = sims[i]->cfg;
-            const int r = c.filter_passes > 0 ? c.filter_passes + (c.filter_compensate ? 1 : 0) : 0;
-            rf = i == 0 ? r : (r == rf ? rf : -1);
-            if (rf < 0) break;
-        }
-        // the staging buffers may still feed an earlier copy
-        HIPCHK(hipStreamSynchronize(st));
-        long long w = 0, wf = 0, wy = 0;
-        for (int i = 0; i < n; ++i) {
-            const Layout &L = sims[i]->L;
-            b->h_table[i] = sims[i]->df;
-            b->h_table[i].nsb = 1;  // batched pushes take every species of a tile at once
-            for (int t = 0; t < L.ntiles; ++t) b->h_work[w++] = make_int2(i, t);
+    return guarded<int>([&]() -> int {
+        if (!b || n < 0 || nsteps < 0 || (n > 0 && !sims)) return fail(PIC_E_ARG, "bad batch call");
+        if (n == 0 || nsteps == 0) return PIC_OK;
+        if (n > b->max_sims) return fail(PIC_E_ARG, "more simulations than the batch holds");
+        hipStream_t st = (hipStream_t)stream;
+        bool same = (int)b->cur.size() == n;
+        for (int i = 0; same && i < n; ++i) same = sims[i] && sims[i]->uid == b->cur[i];
+        if (!same) {
+            long long nwork = 0;
+            for (int i = 0; i < n; ++i) {
+                const pic_sim *s = sims[i];
+                if (!s || s->cfg.fp64 || s->cfg.moving_window || s->cfg.deposit_mode != 0)
+                    return fail(PIC_E_ARG, "batches hold FP32 periodic simulations with the "
+                                           "reduction deposit only");
+                nwork += s->L.ntiles;
+            }
+            if (nwork > b->max_tiles) return fail(PIC_E_ARG, "batch work list too long");
+            // the streaming field kernels need one filter halo for the whole batch
+            int rf = -1;
+            for (int i = 0; i < n; ++i) {
+                const pic_cfg &c = sims[i]->cfg;
+                const int r = c.filter_passes > 0 ? c.filter_passes + (c.filter_compensate ? 1 : 0) : 0;
+                rf = i == 0 ? r : (r == rf ? rf : -1);
+                if (rf < 0) break;
+            }
+            // the staging buffers may still feed an earlier copy
+            HIPCHK(hipStreamSynchronize(st));
+            long long w = 0, wf = 0, wy = 0;
+            for (int i = 0; i < n; ++i) {
+                const Layout &L = sims[i]->L;
+                b->h_table[i] = sims[i]->df;
+                b->h_table[i].nsb = 1;  // batched pushes take every species of a tile at once
+                for (int t = 0; t < L.ntiles; ++t) b->h_work[w++] = make_int2(i, t);
+                if (rf >= 0) {
+                    const int nf = fold_units(L.ntx, L.nty), ny = yee_units(L.nxs, sims[i]->cfg.ny, rf);
+                    if (wf + nf > b->max_tiles * SUNITS_PER_TILE || wy + ny > b->max_tiles * SUNITS_PER_TILE)
+                        return fail(PIC_E_ARG, "batch work list too long");
+                    for (int u = 0; u < nf; ++u) b->h_fwork[wf++] = make_int2(i, u);
+                    for (int u = 0; u < ny; ++u) b->h_ywork[wy++] = make_int2(i, u);
+                }
+            }
+            b->h_batch->nwork = (int)nwork;
+            b->h_batch->nsim = n;
+            b->h_batch->work = b->d_work;
+            b->h_batch->blocks_done = 0;
+            b->h_batch->nfold = (int)wf;
+            b->h_batch->nyee = (int)wy;
+            b->h_batch->fold_work = b->d_fwork;
+            b->h_batch->yee_work = b->d_ywork;
+            HIPCHK(hipMemcpyAsync(b->d_table, b->h_table, (size_t)n * sizeof(SimDev<float>),
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(b->d_work, b->h_work, (size_t)nwork * sizeof(int2),
+                                  hipMemcpyHostToDevice, st));
             if (rf >= 0) {
-                const int nf = fold_units(L.ntx, L.nty), ny = yee_units(L.nxs, sims[i]->cfg.ny, rf);
-                if (wf + nf > b->max_tiles * SUNITS_PER_TILE || wy + ny > b->max_tiles * SUNITS_PER_TILE)
-                    return fail(PIC_E_ARG, "batch work list too long");
-                for (int u = 0; u < nf; ++u) b->h_fwork[wf++] = make_int2(i, u);
-                for (int u = 0; u < ny; ++u) b->h_ywork[wy++] = make_int2(i, u);
+                HIPCHK(hipMemcpyAsync(b->d_fwork, b->h_fwork, (size_t)wf * sizeof(int2),
+                                      hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(b->d_ywork, b->h_ywork, (size_t)wy * sizeof(int2),
+                                      hipMemcpyHostToDevice, st));
+            }
+            HIPCHK(hipMemcpyAsync(b->d_batch, b->h_batch, sizeof(BatchDev), hipMemcpyHostToDevice,
+                                  st));
+            b->cur.resize(n);
+            for (int i = 0; i < n; ++i) b->cur[i] = sims[i]->uid;
+            // one graph serves every work list up to its grid; blocks past the
+            // work count exit at once
+            auto round = [](long long v) { return (int)((v + 1023) / 1024 * 1024); };
+            const int need = round(nwork), need_f = round(wf), need_y = round(wy);
+            auto fits = [](int need_, int grid_) { return need_ <= grid_ && grid_ <= 4 * need_; };
+            if (!b->gexec || rf != b->rf || !fits(need, b->grid) ||
+                (rf >= 0 && (!fits(need_f, b->grid_fold) || !fits(need_y, b->grid_yee)))) {
+                if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+                if (b->graph) (void)hipGraphDestroy(b->graph);
+                b->gexec = nullptr;
+                b->graph = nullptr;
+                HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+                hipError_t le = launch_batch_step<float>(b->d_table, b->d_batch, need, b->cap_stream,
+                                                         rf, need_f, need_y);
+                hipGraph_t g = nullptr;
+                hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+                if (le != hipSuccess || ce != hipSuccess)
+                    return fail(PIC_E_HIP, "batch graph capture failed");
+                b->graph = g;
+                HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+                b->grid = need;
+                b->grid_fold = need_f;
+                b->grid_yee = need_y;
+                b->rf = rf;
             }
         }
-        b->h_batch->nwork = (int)nwork;
-        b->h_batch->nsim = n;
-        b->h_batch->work = b->d_work;
-        b->h_batch->blocks_done = 0;
-        b->h_batch->nfold = (int)wf;
-        b->h_batch->nyee = (int)wy;
-        b->h_batch->fold_work = b->d_fwork;
-        b->h_batch->yee_work = b->d_ywork;
-        HIPCHK(hipMemcpyAsync(b->d_table, b->h_table, (size_t)n * sizeof(SimDev<float>),
-                              hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(b->d_work, b->h_work, (size_t)nwork * sizeof(int2),
-                              hipMemcpyHostToDevice, st));
-        if (rf >= 0) {
-            HIPCHK(hipMemcpyAsync(b->d_fwork, b->h_fwork, (size_t)wf * sizeof(int2),
-                                  hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(b->d_ywork, b->h_ywork, (size_t)wy * sizeof(int2),
-                                  hipMemcpyHostToDevice, st));
-        }
-        HIPCHK(hipMemcpyAsync(b->d_batch, b->h_batch, sizeof(BatchDev), hipMemcpyHostToDevice,
-                              st));
-        b->cur.resize(n);
-        for (int i = 0; i < n; ++i) b->cur[i] = sims[i]->uid;
-        // one graph serves every work list up to its grid; blocks past the
-        // work count exit at once
-        auto round = [](long long v) { return (int)((v + 1023) / 1024 * 1024); };
-        const int need = round(nwork), need_f = round(wf), need_y = round(wy);
-        auto fits = [](int need_, int grid_) { return need_ <= grid_ && grid_ <= 4 * need_; };
-        if (!b->gexec || rf != b->rf || !fits(need, b->grid) ||
-            (rf >= 0 && (!fits(need_f, b->grid_fold) || !fits(need_y, b->grid_yee)))) {
-            if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-            if (b->graph) (void)hipGraphDestroy(b->graph);
-            b->gexec = nullptr;
-            b->graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
-            hipError_t le = launch_batch_step<float>(b->d_table, b->d_batch, need, b->cap_stream,
-                                                     rf, need_f, need_y);
-            hipGraph_t g = nullptr;
-            hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
-            if (le != hipSuccess || ce != hipSuccess)
-                return fail(PIC_E_HIP, "batch graph capture failed");
-            b->graph = g;
-            HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
-            b->grid = need;
-            b->grid_fold = need_f;
-            b->grid_yee = need_y;
-            b->rf = rf;
-        }
-    }
-    for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(b->gexec, st));
-    return PIC_OK;
+        for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(b->gexec, st));
+        return PIC_OK;
+    });
 }
 
 }  // extern "C"
@@ -1234,145 +1301,147 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
                          const pic_serve_opts *opts, pic_result *out, double *step_ms,
                          long long cap_steps, long long *n_steps, void *stream)
 {
-    if (n < 0 || (n > 0 && (!reqs || !out)) || !arena || !opts || ((uintptr_t)arena & 255))
-        return fail(PIC_E_ARG, "bad serving arguments");
-    const int chunk = std::max(1, opts->chunk_steps);
-    const int max_active = opts->batched ? (opts->max_batch > 0 ? opts->max_batch : 256) : 1;
-    if (n_steps) *n_steps = 0;
-    for (int i = 0; i < n; ++i) {
-        std::memset(&out[i], 0, sizeof(out[i]));
-        out[i].status = PIC_E_STATE;
-    }
-    // batch workspace at the start of the arena, the rest is the budget
-    long long max_tiles = 0;
-    for (int i = 0; i < n; ++i) {
-        Layout L;
-        if (layout(&reqs[i].cfg, &L) == PIC_OK) max_tiles += L.ntiles;
-    }
-    max_tiles = std::max(1LL, std::min(max_tiles, 1LL << 22));
-    const size_t bws = align256(pic_batch_mem_bytes(max_active, max_tiles));
-    if (arena_bytes < bws + 256) return fail(PIC_E_NOMEM, "budget smaller than the batch workspace");
-    pic_batch *batch = nullptr;
-    int rc = pic_batch_create(arena, bws, max_active, max_tiles, &batch);
-    if (rc) return rc;
-    hipStream_t sa = (hipStream_t)stream, sb = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t he = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipEventCreate(&e0);
-    if (he == hipSuccess) he = hipEventCreate(&e1);
-    auto teardown = [&] {
-        (void)hipStreamSynchronize(sa);
-        if (sb) (void)hipStreamSynchronize(sb);
-        pic_batch_free(batch);
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        if (sb) (void)hipStreamDestroy(sb);
-    };
-    if (he != hipSuccess) {
-        teardown();
-        return fail(PIC_E_HIP, std::string("serving set-up: ") + hipGetErrorString(he));
-    }
-    char *pool = (char *)arena + bws;
-    const size_t pool_bytes = (arena_bytes - bws) & ~(size_t)255;
-    ArenaAlloc alloc(pool_bytes);
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
-    const auto t0 = std::chrono::steady_clock::now();
-    auto now = [&] {
-        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    };
-    std::vector<int> queue;
-    std::vector<Active> active;
-    std::vector<pic_sim *> sims;
-    int next = 0, done = 0;
-    long long ns = 0;
-    // admit queued requests, first fit in arrival order (one at a time: strictly
-    // in order), initialising them on stream sb while the step stream runs
-    auto admit = [&] {
-        const double tnow = now();
-        while (next < n && reqs[order[next]].arrival_s <= tnow) queue.push_back(order[next++]);
-        for (size_t qi = 0; qi < queue.size() && (int)active.size() < max_active;) {
-            const int r = queue[qi];
-            const size_t need = pic_mem_bytes(&reqs[r].cfg);
-            const bool unbatchable = opts->batched && (reqs[r].cfg.fp64 ||
-                                                       reqs[r].cfg.moving_window ||
-                                                       reqs[r].cfg.deposit_mode != 0);
-            if (need == 0 || unbatchable || align256(need) > pool_bytes) {
-                out[r].status = need == 0 || unbatchable ? PIC_E_ARG : PIC_E_NOMEM;
-                ++done;
+    return guarded<int>([&]() -> int {
+        if (n < 0 || (n > 0 && (!reqs || !out)) || !arena || !opts || ((uintptr_t)arena & 255))
+            return fail(PIC_E_ARG, "bad serving arguments");
+        const int chunk = std::max(1, opts->chunk_steps);
+        const int max_active = opts->batched ? (opts->max_batch > 0 ? opts->max_batch : 256) : 1;
+        if (n_steps) *n_steps = 0;
+        for (int i = 0; i < n; ++i) {
+            std::memset(&out[i], 0, sizeof(out[i]));
+            out[i].status = PIC_E_STATE;
+        }
+        // batch workspace at the start of the arena, the rest is the budget
+        long long max_tiles = 0;
+        for (int i = 0; i < n; ++i) {
+            Layout L;
+            if (layout(&reqs[i].cfg, &L) == PIC_OK) max_tiles += L.ntiles;
+        }
+        max_tiles = std::max(1LL, std::min(max_tiles, 1LL << 22));
+        const size_t bws = align256(pic_batch_mem_bytes(max_active, max_tiles));
+        if (arena_bytes < bws + 256) return fail(PIC_E_NOMEM, "budget smaller than the batch workspace");
+        pic_batch *batch = nullptr;
+        int rc = pic_batch_create(arena, bws, max_active, max_tiles, &batch);
+        if (rc) return rc;
+        hipStream_t sa = (hipStream_t)stream, sb = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t he = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreate(&e0);
+        if (he == hipSuccess) he = hipEventCreate(&e1);
+        auto teardown = [&] {
+            (void)hipStreamSynchronize(sa);
+            if (sb) (void)hipStreamSynchronize(sb);
+            pic_batch_free(batch);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (sb) (void)hipStreamDestroy(sb);
+        };
+        if (he != hipSuccess) {
+            teardown();
+            return fail(PIC_E_HIP, std::string("serving set-up: ") + hipGetErrorString(he));
+        }
+        char *pool = (char *)arena + bws;
+        const size_t pool_bytes = (arena_bytes - bws) & ~(size_t)255;
+        ArenaAlloc alloc(pool_bytes);
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+        const auto t0 = std::chrono::steady_clock::now();
+        auto now = [&] {
+            return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        };
+        std::vector<int> queue;
+        std::vector<Active> active;
+        std::vector<pic_sim *> sims;
+        int next = 0, done = 0;
+        long long ns = 0;
+        // admit queued requests, first fit in arrival order (one at a time: strictly
+        // in order), initialising them on stream sb while the step stream runs
+        auto admit = [&] {
+            const double tnow = now();
+            while (next < n && reqs[order[next]].arrival_s <= tnow) queue.push_back(order[next++]);
+            for (size_t qi = 0; qi < queue.size() && (int)active.size() < max_active;) {
+                const int r = queue[qi];
+                const size_t need = pic_mem_bytes(&reqs[r].cfg);
+                const bool unbatchable = opts->batched && (reqs[r].cfg.fp64 ||
+                                                           reqs[r].cfg.moving_window ||
+                                                           reqs[r].cfg.deposit_mode != 0);
+                if (need == 0 || unbatchable || align256(need) > pool_bytes) {
+                    out[r].status = need == 0 || unbatchable ? PIC_E_ARG : PIC_E_NOMEM;
+                    ++done;
+                    queue.erase(queue.begin() + qi);
+                    continue;
+                }
+                const long long off = alloc.take(need);
+                if (off < 0) {
+                    if (!opts->batched) break;
+                    ++qi;
+                    continue;
+                }
+                pic_sim *sim = nullptr;
+                const int ir = pic_init(&reqs[r].cfg, pool + off, need, sb, &sim);
                 queue.erase(queue.begin() + qi);
-                continue;
+                if (ir) {
+                    alloc.give((size_t)off, need);
+                    out[r].status = ir;
+                    ++done;
+                    continue;
+                }
+                out[r].admit_s = now();
+                active.push_back(Active{r, sim, (size_t)off, need, std::max(0, reqs[r].nsteps)});
             }
-            const long long off = alloc.take(need);
-            if (off < 0) {
-                if (!opts->batched) break;
-                ++qi;
-                continue;
-            }
-            pic_sim *sim = nullptr;
-            const int ir = pic_init(&reqs[r].cfg, pool + off, need, sb, &sim);
-            queue.erase(queue.begin() + qi);
-            if (ir) {
-                alloc.give((size_t)off, need);
-                out[r].status = ir;
+        };
+        auto retire = [&] {
+            for (size_t ai = 0; ai < active.size();) {
+                Active &a = active[ai];
+                if (a.left > 0) {
+                    ++ai;
+                    continue;
+                }
+                out[a.req].status = pic_energy(a.sim, &out[a.req].diag, sa);
+                out[a.req].done_s = now();
+                pic_free(a.sim);
+                alloc.give(a.off, a.bytes);
                 ++done;
+                active.erase(active.begin() + ai);
+            }
+        };
+        while (done < n && rc == PIC_OK) {
+            admit();
+            retire();
+            if (active.empty()) {
+                if (queue.empty() && next < n) {
+                    const double wait = reqs[order[next]].arrival_s - now();
+                    if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+                }
                 continue;
             }
-            out[r].admit_s = now();
-            active.push_back(Active{r, sim, (size_t)off, need, std::max(0, reqs[r].nsteps)});
-        }
-    };
-    auto retire = [&] {
-        for (size_t ai = 0; ai < active.size();) {
-            Active &a = active[ai];
-            if (a.left > 0) {
-                ++ai;
-                continue;
+            // one chunk of the running set, all members in lockstep
+            int k = chunk;
+            sims.clear();
+            for (const Active &a : active) {
+                sims.push_back(a.sim);
+                k = std::min(k, a.left);
             }
-            out[a.req].status = pic_energy(a.sim, &out[a.req].diag, sa);
-            out[a.req].done_s = now();
-            pic_free(a.sim);
-            alloc.give(a.off, a.bytes);
-            ++done;
-            active.erase(active.begin() + ai);
+            (void)hipEventRecord(e0, sa);
+            // a batch of one runs the simulation's own step graph
+            rc = sims.size() > 1 ? pic_batch_step(batch, sims.data(), (int)sims.size(), k, sa)
+                                 : pic_step(sims[0], k, sa);
+            (void)hipEventRecord(e1, sa);
+            if (rc) break;
+            admit();  // while the chunk runs
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (step_ms && ns < cap_steps) step_ms[ns] = ms / k;
+            ++ns;
+            for (Active &a : active)
+                if (std::find(sims.begin(), sims.end(), a.sim) != sims.end()) a.left -= k;
         }
-    };
-    while (done < n && rc == PIC_OK) {
-        admit();
-        retire();
-        if (active.empty()) {
-            if (queue.empty() && next < n) {
-                const double wait = reqs[order[next]].arrival_s - now();
-                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
-            }
-            continue;
-        }
-        // one chunk of the running set, all members in lockstep
-        int k = chunk;
-        sims.clear();
-        for (const Active &a : active) {
-            sims.push_back(a.sim);
-            k = std::min(k, a.left);
-        }
-        (void)hipEventRecord(e0, sa);
-        // a batch of one runs the simulation's own step graph
-        rc = sims.size() > 1 ? pic_batch_step(batch, sims.data(), (int)sims.size(), k, sa)
-                             : pic_step(sims[0], k, sa);
-        (void)hipEventRecord(e1, sa);
-        if (rc) break;
-        admit();  // while the chunk runs
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (step_ms && ns < cap_steps) step_ms[ns] = ms / k;
-        ++ns;
-        for (Active &a : active)
-            if (std::find(sims.begin(), sims.end(), a.sim) != sims.end()) a.left -= k;
-    }
-    for (Active &a : active) pic_free(a.sim);
-    if (n_steps) *n_steps = ns;
-    teardown();
-    return rc;
+        for (Active &a : active) pic_free(a.sim);
+        if (n_steps) *n_steps = ns;
+        teardown();
+        return rc;
+    });
 }

@@ -406,6 +406,22 @@ def test_capacity_overflow_is_reported():
     assert sim.energy()["status"] == PIC_E_CAPACITY
 
 
+def test_particle_count_beyond_the_slots_is_refused_before_any_read():
+    # a count above the species' slots is refused before the arrays are read
+    # or any host buffer is sized by it; the simulation carries on
+    from paper_2106_12485_amd import pic
+    w = thermal64()
+    sim = Simulation(w)
+    one_i = np.zeros(1, np.int32)
+    one_d = np.zeros(1)
+    rc = pic.lib().pic_set_particles(sim._h, 0, 1 << 61, pic._ip(one_i), pic._ip(one_i),
+                                     *[pic._dp(one_d)] * 5, sim._sp())
+    assert rc == PIC_E_CAPACITY
+    assert "slots" in pic.lib().pic_last_error().decode()
+    sim.step(3)
+    assert sim.status() == 0 and sim.count(0) == 65536
+
+
 def test_lwfa_window_run_counts_and_teacher_forced_shift():
     # reduced laser-wakefield geometry with the moving window
     w = lwfa(nx=300, ny=32, lx=6.0, ly=6.4, steps=40, x_plasma=4.0, ppc=(2, 2))
