@@ -728,11 +728,12 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
         }
         return PIC_OK;
     }
-    if (nsteps >= GRAPH_STEPS && !s->gexec_n) {
+    // both graphs on the first call, so that later calls only replay
+    if (!s->gexec_n) {
         const int rc = capture_steps(s, d, GRAPH_STEPS, &s->graph_n, &s->gexec_n);
         if (rc) return rc;
     }
-    if (nsteps % GRAPH_STEPS && !s->gexec) {
+    if (!s->gexec) {
         const int rc = capture_steps(s, d, 1, &s->graph, &s->gexec);
         if (rc) return rc;
     }
