@@ -127,3 +127,34 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_traffic_is_null_unless_the_profile_matches_the_sources(tmp_path, monkeypatch):
+    # the roofline's measured traffic is reported only while the committed
+    # counter summary was taken on the current kernel sources and build flags
+    import hashlib
+    import bench
+    pkg = os.path.join(ROOT, "paper_2106_12485_amd")
+
+    def sha(*p):
+        return hashlib.sha256(open(os.path.join(pkg, *p), "rb").read()).hexdigest()
+
+    good = {"kernel_source_sha256": sha("csrc", "pic_kernels.hip"),
+            "header_source_sha256": sha("csrc", "pic_dev.h"),
+            "build_source_sha256": sha("build.py"),
+            "traffic_bytes_per_launch": "123456789"}
+
+    def write(vals):
+        f = tmp_path / "traffic.md"
+        f.write_text("# summary\n\n" + "".join("    %s %s\n" % kv for kv in vals.items()))
+        monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(f))
+
+    write(good)
+    assert bench.measured_traffic() == 123456789.0
+    for key in ("kernel_source_sha256", "header_source_sha256", "build_source_sha256"):
+        write(dict(good, **{key: "0" * 64}))
+        assert bench.measured_traffic() is None, key
+    write({k: v for k, v in good.items() if k != "traffic_bytes_per_launch"})
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic() is None
