@@ -158,3 +158,28 @@ def test_bench_traffic_is_null_unless_the_profile_matches_the_sources(tmp_path, 
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
+
+
+def test_product_code_does_not_reach_the_oracle():
+    # the oracle is test infrastructure: no module of the package imports it,
+    # and bench.py reaches it only from its CPU-baseline leg
+    import ast
+    pkg = os.path.join(ROOT, "paper_2106_12485_amd")
+
+    def imports(tree):
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                yield from (a.name.split(".")[0] for a in node.names)
+            elif isinstance(node, ast.ImportFrom) and node.module:
+                yield node.module.split(".")[0]
+
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            tree = ast.parse(open(os.path.join(pkg, name)).read())
+            assert "oracle" not in set(imports(tree)), name
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = [f.name for f in tree.body if isinstance(f, ast.FunctionDef)
+             and "oracle" in set(imports(f))]
+    assert users == ["cpu_baseline"], users
+    assert "oracle" not in {m for n in tree.body if not isinstance(n, ast.FunctionDef)
+                            for m in imports(n)}
