@@ -183,3 +183,15 @@ def test_product_code_does_not_reach_the_oracle():
     assert users == ["cpu_baseline"], users
     assert "oracle" not in {m for n in tree.body if not isinstance(n, ast.FunctionDef)
                             for m in imports(n)}
+
+
+def test_oracle_and_hip_sources_share_no_code():
+    # neither side includes a file of the other
+    import re
+    inc = re.compile(r'#\s*include\s*"([^"]+)"')
+    csrc = os.path.join(ROOT, "paper_2106_12485_amd", "csrc")
+    for name in os.listdir(csrc):
+        for f in inc.findall(open(os.path.join(csrc, name)).read()):
+            assert "oracle" not in f, (name, f)
+    for f in inc.findall(open(os.path.join(ROOT, "oracle", "pic_oracle.c")).read()):
+        assert not f.startswith("pic") or f.startswith("pic_oracle"), f
