@@ -1,0 +1,117 @@
+"""The index arithmetic of the current fold, checked on the CPU.
+
+Each tile's current block covers its own cells plus one guard column/row
+below and two above, with periodic wrap; a cell's folded current is the sum
+of the block entries of every tile whose block covers it.  The device code
+(`fold_s_body` and `fold_cell` in pic_kernels.hip) finds those entries by
+index arithmetic over the 3 x 3 neighbouring tiles, with a fast path for
+full-height tiles at least 3 columns wide.  Both selections are restated here
+and compared, cell by cell over many grid shapes (ragged last tiles, one and
+two tiles per axis, window storage widths), with coverage taken straight
+from its definition: all (tile, block entry) pairs that land on the cell.
+"""
+import itertools
+import random
+import pytest
+
+
+TX = TY = 16
+
+
+def tiles(n):
+    return [(a, min(TX, n - TX * a)) for a in range((n + TX - 1) // TX)]
+
+
+def brute(nxs, ny, gx, gy):
+    """Every (tile x, block column, tile y, block row) whose entry is the cell."""
+    xs = [(a, px + 1) for a, w in tiles(nxs) for px in range(-1, w + 2)
+          if (TX * a + px) % nxs == gx]
+    ys = [(b, py + 1) for b, h in tiles(ny) for py in range(-1, h + 2)
+          if (TY * b + py) % ny == gy]
+    return sorted((a, cx, b, cy) for (a, cx), (b, cy) in itertools.product(xs, ys))
+
+
+def general(nxs, ny, gx, gy):
+    """The 3 x 3 neighbour search, in its (oy, ox) order."""
+    ntx, nty = (nxs + TX - 1) // TX, (ny + TY - 1) // TY
+    tx, ty = gx // TX, gy // TY
+    lx, ly = gx - TX * tx, gy - TY * ty
+    w, h = min(TX, nxs - TX * tx), min(TY, ny - TY * ty)
+    out = []
+    for oy in (-1, 0, 1):
+        tyn = (ty + oy) % nty
+        hn = min(TY, ny - TY * tyn)
+        py = ly if oy == 0 else (ly + hn if oy < 0 else ly - h)
+        if py < -1 or py >= hn + 2:
+            continue
+        for ox in (-1, 0, 1):
+            txn = (tx + ox) % ntx
+            wn = min(TX, nxs - TX * txn)
+            px = lx if ox == 0 else (lx + wn if ox < 0 else lx - w)
+            if px < -1 or px >= wn + 2:
+                continue
+            out.append((txn, px + 1, tyn, py + 1))
+    return out
+
+
+def fast(nxs, ny, gx, gy):
+    """The path for a full-height tile at least 3 columns wide (None otherwise)."""
+    ntx, nty = (nxs + TX - 1) // TX, (ny + TY - 1) // TY
+    tx, ty = gx // TX, gy // TY
+    lx, ly = gx - TX * tx, gy - TY * ty
+    w, h = min(TX, nxs - TX * tx), min(TY, ny - TY * ty)
+    if not (h == TY and w >= 3):
+        return None
+    txl, txr = (tx - 1) % ntx, (tx + 1) % ntx
+    wl = min(TX, nxs - TX * txl)
+    xo = -1 if lx < 2 else (1 if lx == w - 1 else 0)
+    txn = txl if xo < 0 else (txr if xo > 0 else tx)
+    cxo, cxn = lx + 1, (lx + wl + 1 if xo < 0 else (0 if xo > 0 else lx + 1))
+
+    def level(tyn, row):
+        if xo < 0:
+            return [(txn, cxn, tyn, row), (tx, cxo, tyn, row)]
+        if xo > 0:
+            return [(tx, cxo, tyn, row), (txn, cxn, tyn, row)]
+        return [(tx, cxo, tyn, row)]
+
+    out = []
+    if ly < 2:
+        tyl = (ty - 1) % nty
+        out += level(tyl, ly + min(TY, ny - TY * tyl) + 1)
+    out += level(ty, ly + 1)
+    if ly == TY - 1:
+        out += level((ty + 1) % nty, 0)
+    return out
+
+
+def shapes():
+    # sizes the library accepts: no one-cell tile along either axis
+    ok = [n for n in range(2, 70) if n % TX != 1]
+    rng = random.Random(7)
+    yield from [(4, 4), (2, 2), (3, 70), (18, 20), (34, 18), (32, 32), (16, 16), (48, 34)]
+    for _ in range(40):
+        yield rng.choice(ok), rng.choice(ok)
+    # moving-window storage widths are multiples of 16
+    yield from [(32, 20), (64, 9), (80, 34)]
+
+
+@pytest.mark.parametrize("nxs,ny", list(shapes()))
+def test_fold_selects_exactly_the_covering_block_entries(nxs, ny):
+    for gy in range(ny):
+        for gx in range(nxs):
+            g = general(nxs, ny, gx, gy)
+            assert sorted(g) == brute(nxs, ny, gx, gy), (gx, gy)
+            f = fast(nxs, ny, gx, gy)
+            if f is not None:
+                # the same entries, added in the same order
+                assert f == g, (gx, gy)
+
+
+def test_a_one_cell_tile_would_be_missed():
+    # why a grid may not leave a one-cell tile: the guard columns of the tile
+    # two to the left then reach over it, beyond the 3 x 3 neighbour search
+    nxs, ny = 33, 16
+    misses = [(gx, gy) for gy in range(ny) for gx in range(nxs)
+              if sorted(general(nxs, ny, gx, gy)) != brute(nxs, ny, gx, gy)]
+    assert misses
