@@ -115,3 +115,50 @@ def test_a_one_cell_tile_would_be_missed():
     misses = [(gx, gy) for gy in range(ny) for gx in range(nxs)
               if sorted(general(nxs, ny, gx, gy)) != brute(nxs, ny, gx, gy)]
     assert misses
+
+
+# ---------------------------------------------------------------------------
+# the streaming field kernels' work split: strips of columns by rows
+# ---------------------------------------------------------------------------
+YS_S = 6
+
+
+def strip_w(rf):
+    return 63 - 2 * max(1, rf)
+
+
+@pytest.mark.parametrize("rf", [0, 1, 2, 3, 4])
+def test_yee_strips_own_every_cell_exactly_once(rf):
+    # a wavefront of 64 lanes holds columns c0 - P .. c0 + 63 - P and owns
+    # lanes P .. P + W - 1 (P = max(1, rf)); the rf filter passes leave lanes
+    # rf .. 63 - rf exact, the Yee halo is one lane below and two above
+    P, W = max(1, rf), strip_w(rf)
+    assert P >= rf and P + W <= 64 - rf and P - 1 >= 0 and P + W + 1 <= 63
+    rng = random.Random(rf)
+    for nxs, ny in [(2, 2), (3, 70), (61, 7), (62, 12), (64, 64), (130, 40)] + \
+            [(rng.randrange(2, 300), rng.randrange(2, 50)) for _ in range(20)]:
+        ncg = (nxs + W - 1) // W
+        units = ncg * ((ny + YS_S - 1) // YS_S)
+        seen = {}
+        for blk in range(units):
+            cg, r0 = blk % ncg, (blk // ncg) * YS_S
+            nr = min(YS_S, ny - r0)
+            for L in range(64):
+                cx = cg * W + L - P
+                if not (P <= L < P + W and cx < nxs):
+                    continue
+                for m in range(nr):
+                    key = (cx, r0 + m)
+                    assert key not in seen, (nxs, ny, key)
+                    seen[key] = blk
+        assert len(seen) == nxs * ny, (nxs, ny)
+
+
+def test_the_model_uses_the_device_constants():
+    import os
+    import re
+    h = open(os.path.join(os.path.dirname(__file__), "..", "paper_2106_12485_amd", "csrc",
+                          "pic_dev.h")).read()
+    assert re.search(r"constexpr int TX = 16\b", h) and re.search(r"constexpr int TY = 16\b", h)
+    assert re.search(r"constexpr int YS_S = %d;" % YS_S, h)
+    assert "return 63 - 2 * (rf > 1 ? rf : 1);" in h
