@@ -1,14 +1,15 @@
-"""The index arithmetic of the current fold, checked on the CPU.
+"""Index maps of the device code, restated and checked on the CPU.
 
-Each tile's current block covers its own cells plus one guard column/row
-below and two above, with periodic wrap; a cell's folded current is the sum
-of the block entries of every tile whose block covers it.  The device code
-(`fold_s_body` and `fold_cell` in pic_kernels.hip) finds those entries by
-index arithmetic over the 3 x 3 neighbouring tiles, with a fast path for
-full-height tiles at least 3 columns wide.  Both selections are restated here
-and compared, cell by cell over many grid shapes (ragged last tiles, one and
-two tiles per axis, window storage widths), with coverage taken straight
-from its definition: all (tile, block entry) pairs that land on the cell.
+- The current fold: each tile's current block covers its own cells plus one
+  guard column/row below and two above, with periodic wrap; a cell's folded
+  current is the sum of the block entries of every tile whose block covers it.
+  The device code (`fold_s_body`, `fold_cell` in pic_kernels.hip) finds those
+  entries by index arithmetic over the 3 x 3 neighbouring tiles, with a fast
+  path for full-height tiles at least 3 columns wide.  Both are compared, cell
+  by cell over many grid shapes, with coverage taken from its definition: all
+  (tile, block entry) pairs that land on the cell.
+- The streaming field kernels' strips own every cell exactly once.
+- The particle hand-off delivers every leaver to exactly one tile.
 """
 import itertools
 import random
@@ -162,3 +163,42 @@ def test_the_model_uses_the_device_constants():
     assert re.search(r"constexpr int TX = 16\b", h) and re.search(r"constexpr int TY = 16\b", h)
     assert re.search(r"constexpr int YS_S = %d;" % YS_S, h)
     assert "return 63 - 2 * (rf > 1 ? rf : 1);" in h
+
+
+# ---------------------------------------------------------------------------
+# the particle hand-off: each leaver is picked up by exactly one tile
+# ---------------------------------------------------------------------------
+def dir_index(dtx, dty):
+    k = (dtx + 1) + 3 * (dty + 1)  # 0..8 without the centre 4
+    return k if k < 4 else k - 1
+
+
+def neighbour_slots(t, ntx, nty):
+    """(neighbour tile, direction wanted) for the 8 slots of tile t."""
+    tx, ty = t % ntx, t // ntx
+    out = []
+    for k in range(8):
+        k9 = k if k < 4 else k + 1
+        ox, oy = k9 % 3 - 1, k9 // 3 - 1
+        nb = (tx + ox) % ntx + ((ty + oy) % nty) * ntx
+        out.append((nb, dir_index(-ox, -oy)))
+    return out
+
+
+@pytest.mark.parametrize("ntx,nty", [(1, 1), (1, 3), (2, 1), (2, 2), (3, 2), (4, 5)])
+def test_every_leaver_is_taken_by_exactly_one_tile(ntx, nty):
+    # a leaver of tile a stepping by (dtx, dty) (0 along an axis of one tile,
+    # which wraps onto itself) is read from a's outbox by the slots of the
+    # tile it lands in whose neighbour is a and whose wanted direction is its own
+    for a in range(ntx * nty):
+        ax, ay = a % ntx, a // ntx
+        for dtx, dty in itertools.product((-1, 0, 1), repeat=2):
+            if (dtx, dty) == (0, 0) or (ntx == 1 and dtx) or (nty == 1 and dty):
+                continue
+            dest = (ax + dtx) % ntx + ((ay + dty) % nty) * ntx
+            takers = [(b, k) for b in range(ntx * nty)
+                      for k, (nb, want) in enumerate(neighbour_slots(b, ntx, nty))
+                      if nb == a and want == dir_index(dtx, dty)]
+            assert len(takers) == 1 and takers[0][0] == dest, (a, dtx, dty, takers)
+    assert sorted(dir_index(x, y) for x, y in itertools.product((-1, 0, 1), repeat=2)
+                  if (x, y) != (0, 0)) == list(range(8))
