@@ -206,14 +206,17 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->dt_dy = (R)(d->dt_d / d->dy_d);
     d->jxs = (R)(d->dx_d / d->dt_d);
     d->jys = (R)(d->dy_d / d->dt_d);
-    // Fixed-point scale 2^-e of the LDS sums.  One current or charge term of a
-    // particle is at most |q_p| (|v| < 1; weights and path fractions <= 1), so
-    // one LDS entry never exceeds the sum of |q_p| over the slots of the tile.
-    // Take the largest e that keeps that bound below 2^62.
+    // Fixed-point scale 2^-e of the LDS sums.  The terms one particle adds to
+    // one LDS entry over its step total at most |q_p| (|v| < 1; weights and
+    // path fractions <= 1).  A push block takes its tile's particles and the
+    // arrivals of the last hand-off; unless it flags a capacity error, those
+    // that stay fit the tile's slots and those that leave fit the outbox, so
+    // an entry never exceeds the sum of |q_p| over slots + outbox slots of
+    // every species.  Take the largest e that keeps that bound below 2^62.
     double bound = 0.0;
     for (int s = 0; s < c->n_species; ++s) {
         const pic_species_cfg &p = c->sp[s];
-        bound += (double)L.cap[s] * p.density / (p.ppc_x * p.ppc_y);
+        bound += (double)(L.cap[s] + L.cap_out) * p.density / (p.ppc_x * p.ppc_y);
     }
     const int e = bound > 0 ? std::min(120, 62 - (int)std::ceil(std::log2(bound))) : 60;
     d->jq = (R)std::ldexp(1.0, sizeof(R) == 4 ? e - 32 : e);
