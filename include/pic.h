@@ -201,7 +201,9 @@ int pic_free(pic_sim *sim);
 
 /* Replace all particles of species sp with n particles given as host arrays
  * (ix in [0, nx), iy in [0, ny), x, y in [0, 1)); values are rounded to the
- * working precision.  PIC_E_CAPACITY if a tile overflows.  Synchronises. */
+ * working precision.  PIC_E_CAPACITY if a tile overflows, or at once (the
+ * arrays unread) if n exceeds the species' slots over all tiles.
+ * Synchronises. */
 int pic_set_particles(pic_sim *sim, int sp, long long n, const int *ix, const int *iy,
                       const double *x, const double *y, const double *ux,
                       const double *uy, const double *uz, void *stream);
