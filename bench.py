@@ -77,7 +77,7 @@ def parse():
                     help="how tiles' currents are combined: per-tile blocks summed by a fold "
                          "launch, or four checkerboard colours adding straight into J")
     ap.add_argument("--fp64", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3,
+    ap.add_argument("--cpu-steps", type=int, default=5,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up and timed steps only (for rocprofv3)")
