@@ -20,7 +20,7 @@ from parity_util import (TOL_STEP_FP32, TOL_STEP_FP64, add_species, compare_part
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-if not torch.cuda.is_available():  # pragma: no cover - the GPU suite runs on a GPU machine
+if not torch.cuda.is_available():  # pragma: no cover - the GPU suite needs an MI355X
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2106_12485_amd import PIC_E_CAPACITY, PicError, Simulation  # noqa: E402
