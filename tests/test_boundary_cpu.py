@@ -195,3 +195,31 @@ def test_oracle_and_hip_sources_share_no_code():
             assert "oracle" not in f, (name, f)
     for f in inc.findall(open(os.path.join(ROOT, "oracle", "pic_oracle.c")).read()):
         assert not f.startswith("pic") or f.startswith("pic_oracle"), f
+
+
+def test_binding_marshals_every_configuration_field():
+    # the binding only copies the workload into the C struct: field by field
+    from inputs import lwfa, weibel512
+    from paper_2106_12485_amd import pic
+    w = lwfa()
+    c = pic.make_cfg(w, fp64=True, load=False, capacity_factor=2.5)
+    assert (c.nx, c.ny, c.lx, c.ly, c.dt) == (w.nx, w.ny, w.lx, w.ly, w.dt)
+    assert (c.moving_window, c.filter_passes, c.filter_compensate) == (1, w.filter_passes, 1)
+    assert (c.fp64, c.load, c.capacity_factor, c.deposit_mode) == (1, 0, 2.5, 0)
+    assert c.seed == w.seed and c.n_species == len(w.species)
+    s, t = w.species[0], c.sp[0]
+    assert (t.q_over_m, t.density, t.x_lo, t.ppc_x, t.ppc_y) == (s.qm, s.density, s.x_lo,
+                                                                  s.ppc[0], s.ppc[1])
+    assert t.x_hi == min(s.x_hi, 1e300)
+    assert list(t.uth) == list(s.uth) and list(t.ufl) == list(s.ufl)
+    L = w.laser
+    assert c.laser.on == 1 and (c.laser.a0, c.laser.omega0, c.laser.W0, c.laser.fwhm,
+                                c.laser.x_center, c.laser.focus, c.laser.axis,
+                                c.laser.pol_angle) == (L.a0, L.omega0, L.W0, L.fwhm,
+                                                       L.x_center, L.focus, L.axis, L.pol)
+    # the workload's own capacity factor unless one is given; the other deposit
+    w = weibel512()
+    assert pic.make_cfg(w).capacity_factor == w.capacity_factor
+    assert pic.make_cfg(w, capacity_factor=4.0).capacity_factor == 4.0
+    assert pic.make_cfg(w, deposit="commutative").deposit_mode == 1
+    assert pic.make_cfg(w).laser.on == 0
