@@ -3,7 +3,7 @@ import math
 
 import numpy as np
 
-from inputs import clouds1024, lwfa2000x512, serving_requests, thermal64, weibel512
+from inputs import clouds1024, lwfa2000x512, lwfa8000, serving_requests, thermal64, weibel512
 
 
 def test_serving_stream_recipe():
@@ -56,3 +56,8 @@ def test_benchmark_workloads_have_the_stated_sizes():
     assert w.species[0].ppc[0] * w.species[0].ppc[1] == 16 and w.steps == 4000
     w = thermal64()
     assert (w.nx, w.ny, w.species[0].ppc) == (64, 64, (4, 4))
+    # the precision study keeps the 2000 x 256 run's cell and step, plasma everywhere
+    w = lwfa8000()
+    assert (w.nx, w.ny, w.lx, w.ly, w.dt) == (8000, 512, 160.0, 102.4, 0.014)
+    assert w.nx * w.ny * w.species[0].ppc[0] * w.species[0].ppc[1] == 65_536_000
+    assert w.species[0].x_lo < 0 and w.dt * math.hypot(w.nx / w.lx, w.ny / w.ly) < 1
