@@ -13,8 +13,8 @@
 """
 import itertools
 import random
-import pytest
 
+import pytest
 
 TX = TY = 16
 
