@@ -116,6 +116,14 @@ int layout(const pic_cfg *c, Layout *L)
     if (c->deposit_mode == 1 && (c->moving_window || (L->ntx & 1) || (L->nty & 1)))
         return fail(PIC_E_ARG, "the commutative deposit needs a periodic box with an even "
                                "number of 16-cell tiles along each axis");
+    // A tile block reaches one cell below and two above its tile.  Same-colour
+    // tiles are two tiles apart, with one tile of width w between them (or the
+    // last tile, across the periodic seam), so their blocks are disjoint only
+    // if that tile is at least 3 cells wide: every middle tile is 16 wide, the
+    // last one n % 16.
+    if (c->deposit_mode == 1 && (L->nxs % TX == 2 || c->ny % TY == 2))
+        return fail(PIC_E_ARG, "the commutative deposit needs the last tile along each axis "
+                               "to be at least 3 cells wide (n % 16 != 2)");
     L->ntiles = L->ntx * L->nty;
     L->rs = c->fp64 ? 8 : 4;
     L->plane = (size_t)L->nxs * c->ny;

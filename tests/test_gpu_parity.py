@@ -1,9 +1,13 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
 
 Each one-step test drives both sides from the same state (FP32-representable
-particles and fields) and compares the current before and after the filter,
-the six field planes and the particle set after one step.  Tolerance: relative
-L2 <= 1e-5 per quantity for the FP32 path, 1e-11 for the FP64 path.
+particles and fields) and compares, after one step, every component of the
+current before and after the filter (Jx, Jy, Jz) and of the fields (Ex .. Bz)
+by relative L2 and element by element, and every particle paired one to one
+with its oracle counterpart, component by component.  Tolerances (FP32 path;
+FP64 path in brackets): relative L2 <= 1e-5 [1e-11] per component;
+max |gpu - oracle| <= 1e-5 [1e-11] * max |oracle| per component; positions
+within 2e-6 [1e-12] cells and momenta within 1e-5 [1e-11] of the largest |u|.
 """
 import math
 import os
@@ -14,8 +18,8 @@ import pytest
 
 from inputs import (LaserSpec, SpeciesSpec, Workload, clouds1024, lwfa, lwfa2000x512,
                     random_particles, thermal64, weibel512)
-from parity_util import (TOL_STEP_FP32, TOL_STEP_FP64, add_species, compare_particles,
-                         oracle_from_workload, oracle_mirror, rel_l2, round_to_f32)
+from parity_util import (TOL_STEP_FP32, add_species, compare_state,
+                         oracle_from_workload, oracle_mirror, round_to_f32)
 
 pytestmark = pytest.mark.gpu
 
@@ -26,10 +30,6 @@ if not torch.cuda.is_available():  # pragma: no cover - the GPU suite needs an M
 from paper_2106_12485_amd import PIC_E_CAPACITY, PicError, Simulation  # noqa: E402
 
 
-def tol(fp64):
-    return TOL_STEP_FP64 if fp64 else TOL_STEP_FP32
-
-
 def step_both(sim, o, direct=False):
     if direct:
         sim.deposit()
@@ -37,19 +37,6 @@ def step_both(sim, o, direct=False):
     else:
         sim.step(1)
     o.step(1)
-
-
-def compare_state(sim, o, w, fp64=False, what=""):
-    t = tol(fp64)
-    errs = dict(J=rel_l2(sim.get_current(False), o.get_current(False)),
-                Jf=rel_l2(sim.get_current(True), o.get_current(True)),
-                F=rel_l2(sim.get_fields(), o.get_fields()))
-    for k in range(len(w.species)):
-        errs["p%d" % k] = compare_particles(sim.get_particles(k), o.get_particles(k), w.nx, w.ny,
-                                            window=w.moving_window, tol=t)
-    bad = {k: v for k, v in errs.items() if not v <= t}
-    assert not bad, (what, errs)
-    return errs
 
 
 def random_state(w, rng, uth=0.4, famp=0.2, n_per_species=None):
@@ -457,16 +444,112 @@ def _full_size_parity(w, nsteps, deposit="reduction"):
     return compare_state(sim, om, w, False, w.name)
 
 
-def test_clouds_1024_full_size_teacher_forced():
+def _mirror_step(sim, w, what):
+    om = oracle_mirror(sim, w)
+    om.set_threads(min(16, os.cpu_count() or 1))
+    step_both(sim, om)
+    return compare_state(sim, om, w, False, what)
+
+
+def _energy_run(w, checkpoints, tf_steps, oracle_steps, bounds):
+    """Run workload w over its whole length on the FP32 path and, beside it,
+    on the FP64 GPU path, both from the library's own load.
+      - total energy of the FP32 run against a free-running FP64 oracle run
+        from its own load, every 10 steps over the first oracle_steps steps;
+      - FP32 against FP64 GPU total energy, and the drift of both, at the
+        checkpoints;
+      - a teacher-forced step against the oracle after each step count in
+        tf_steps (the step is one of the run's own);
+      - device status at every checkpoint.
+    bounds: (FP32 vs oracle, FP32 vs FP64 GPU, absolute drift of either),
+    each relative to the initial total energy W(0).  Returns the two
+    simulations, the initial counts and the history."""
+    s32 = Simulation(w)
+    s64 = Simulation(w, fp64=True)
+    o = oracle_from_workload(w)
+    add_species(o, w, load=True)
+    o.set_threads(min(16, os.cpu_count() or 1))
+    ns = len(w.species)
+    n0 = [s32.count(k) for k in range(ns)]
+    assert n0 == [s64.count(k) for k in range(ns)] == [o.count(k) for k in range(ns)]
+    W0 = o.energy()["total"]
+    assert abs(s32.energy()["total"] / W0 - 1) < 1e-6
+    assert abs(s64.energy()["total"] / W0 - 1) < 1e-12
+    b_ora, b_64, b_drift = bounds
+    dev_ora, hist = [], []
+    events = sorted(set(checkpoints) | set(tf_steps) | set(range(10, oracle_steps + 1, 10)))
+    done = 0
+
+    def advance(k):
+        s32.step(k)
+        s64.step(k)
+        if done < oracle_steps:
+            o.step(k)
+
+    for n in events:
+        assert n >= done, (n, done)
+        if n > done:
+            advance(n - done)
+            done = n
+        if n <= oracle_steps and n % 10 == 0:
+            dev_ora.append(abs(s32.energy()["total"] - o.energy()["total"]) / W0)
+        if n in checkpoints:
+            a, b = s32.energy(), s64.energy()
+            hist.append((n, a["total"] / W0 - 1, b["total"] / W0 - 1,
+                         abs(a["total"] - b["total"]) / W0))
+            print("step %4d  drift32 %+.3e  drift64 %+.3e  |32-64| %.3e  gauss %.2e  cont %.2e"
+                  % (n, hist[-1][1], hist[-1][2], hist[-1][3], a["gauss_res_max"],
+                     a["cont_res_max"]), flush=True)
+            assert a["status"] == 0 and b["status"] == 0, n
+        if n in tf_steps:
+            om = oracle_mirror(s32, w)
+            om.set_threads(min(16, os.cpu_count() or 1))
+            s64.step(1)
+            if done < oracle_steps:
+                o.step(1)
+            step_both(s32, om)
+            compare_state(s32, om, w, False, "%s after %d steps" % (w.name, n))
+            om.close()
+            done += 1
+    o.close()
+    print("energy vs oracle, worst over %d steps: %.3e" % (oracle_steps, max(dev_ora)), flush=True)
+    assert max(dev_ora) < b_ora, dev_ora
+    assert max(h[3] for h in hist) < b_64, hist
+    assert max(max(abs(h[1]), abs(h[2])) for h in hist) < b_drift, hist
+    assert s32.status() == 0 and s64.status() == 0
+    return s32, s64, n0, hist
+
+
+@pytest.mark.timeout(900)
+def test_clouds_1024_whole_run_energy_and_teacher_forced_steps():
+    """The two-cloud run (16.8M particles) over its stated 1000 steps: no tile
+    or outbox runs out of slots while the clouds interpenetrate; total energy
+    against the oracle over a 30-step prefix (bound 1e-4 of W(0), the paper's
+    round-off yardstick, as for the thermal run), FP32 against FP64 GPU and the
+    drift of both every 100 steps; teacher-forced steps as the 6th, 501st and
+    1000th steps; particle counts conserved (periodic box)."""
     w = clouds1024()
-    errs = _full_size_parity(w, 5)
-    assert errs["J"] < TOL_STEP_FP32
+    s32, s64, n0, hist = _energy_run(
+        w, checkpoints=range(100, 1001, 100), tf_steps=(5, 500, 999), oracle_steps=30,
+        bounds=(1e-4, 1e-3, 2e-2))
+    assert [s32.count(k) for k in range(2)] == n0 == [s64.count(k) for k in range(2)]
+    e = s32.energy()
+    assert e["step"] == 1000
 
 
-def test_lwfa_2000x256_full_size_teacher_forced():
+@pytest.mark.timeout(900)
+def test_lwfa_2000x256_whole_run_energy_and_teacher_forced_steps():
+    """The 2000 x 256 laser-wakefield run over its stated 500 steps: total
+    energy against a free-running oracle over all 500 steps (the cold plasma
+    is driven by the laser, not chaotic), FP32 against FP64 GPU every 50
+    steps, teacher-forced steps at 12, 250 and 500 steps, window shifts and
+    particle counts against the oracle's."""
     w = lwfa()
-    errs = _full_size_parity(w, 12)
-    assert errs["F"] < TOL_STEP_FP32
+    s32, s64, n0, hist = _energy_run(
+        w, checkpoints=range(50, 501, 50), tf_steps=(12, 250, 499), oracle_steps=500,
+        bounds=(1e-4, 1e-4, 5e-2))
+    e = s32.energy()
+    assert e["step"] == 500 and e["nshift"] == int(500 * w.dt / w.dx + 1e-9)
 
 
 @pytest.mark.timeout(900)
@@ -534,6 +617,8 @@ COMMUTATIVE_CASES = {
     # name: (workload, fp64); even tile counts, ragged last tiles
     "ragged_56x56_comp": (two_species(56, 56, 5.6, 5.6, filter_passes=1, filter_compensate=True),
                           False),
+    # the narrowest last tile the commutative deposit accepts: 3 cells
+    "last_tile_3_51x51": (two_species(51, 51, 5.1, 5.1, filter_passes=1), False),
     "two_tiles_24x32": (two_species(24, 32, 2.4, 3.2, filter_passes=1), False),
     "fp64_64x32": (two_species(64, 32, 6.4, 3.2, filter_passes=2), True),
 }
@@ -590,3 +675,100 @@ def test_lwfa_2000x512_paper_scale_run():
     om.set_threads(min(16, os.cpu_count() or 1))
     step_both(sim, om)
     compare_state(sim, om, w, False, w.name)
+
+
+# ---------------------------------------------------------------------------
+# floating-point edge cases of the move and of the gather (FP32 offsets)
+# ---------------------------------------------------------------------------
+def edge_particles(w, rng, fp64):
+    """Particles placed on the edges of the cell update and of the deposit
+    split, plus random fillers.  With zero fields the momenta are unchanged
+    by the push, so the displacement is dt/dx * u / gamma to within rounding.
+    Returns the particle dict; d = dt/dx = dt/dy."""
+    d = w.dt / w.dx
+    assert abs(w.dt / w.dy - d) < 1e-15
+    tiny = 2.0 ** -31
+    below1 = 1.0 - 2.0 ** -24          # the largest FP32 offset below 1
+    rows = []
+
+    def add(ix, iy, x, y, ddx, ddy, uz=0.0):
+        # proper velocity that moves by (ddx, ddy) cells: v = dd / d, u = v gamma
+        vx, vy = ddx / d, ddy / d
+        g = 1.0 / math.sqrt(1.0 - vx * vx - vy * vy)
+        rows.append((ix, iy, x, y, vx * g, vy * g, uz))
+
+    for ix, iy in ((5, 7), (15, 16), (16, 15), (0, 0), (w.nx - 1, w.ny - 1)):
+        # x + dx in (-2^-25, 0): adding 1 rounds to exactly 1 in FP32
+        add(ix, iy, tiny, 0.3, -1e-8, 0.0)
+        add(ix, iy, 0.3, tiny, 0.0, -1e-8)
+        # landing on exactly 1.0 in FP32 (a tie rounded to even): the offset
+        # below 1 moved by 3/4 of its ulp; the oracle stays just below 1
+        add(ix, iy, below1, 0.6, 0.75 * 2.0 ** -24, 0.0)
+        add(ix, iy, 0.6, below1, 0.0, 0.75 * 2.0 ** -24)
+        # moving right across the edge from just below it
+        add(ix, iy, below1, 0.2, 0.3, 0.1)
+        # exact corner crossings: both edges at the same path fraction
+        add(ix, iy, 0.75, 0.75, 0.45, 0.45)
+        add(ix, iy, 0.25, 0.25, -0.45, -0.45)
+        add(ix, iy, 0.75, 0.25, 0.45, -0.45)
+        add(ix, iy, 0.25, 0.75, -0.45, 0.45, uz=0.3)
+        # no motion along one axis, or none at all
+        add(ix, iy, 0.3, 0.9, 0.0, 0.3)
+        add(ix, iy, 0.9, 0.3, 0.3, 0.0, uz=-0.2)
+        add(ix, iy, 0.4, 0.6, 0.0, 0.0)
+        # starting exactly on the cell's lower edges
+        add(ix, iy, 0.0, 0.5, -0.2, 0.0)
+        add(ix, iy, 0.5, 0.0, 0.0, 0.2)
+        add(ix, iy, 0.0, 0.0, 0.1, -0.1)
+    a = np.array(rows)
+    n_fill = 2000
+    fill = random_particles(rng, w.nx, w.ny, n_fill, uth=0.3)
+    p = dict(ix=np.concatenate([a[:, 0], fill["ix"]]).astype(np.int32),
+             iy=np.concatenate([a[:, 1], fill["iy"]]).astype(np.int32))
+    for k, c in zip(("x", "y", "ux", "uy", "uz"), range(2, 7)):
+        p[k] = np.concatenate([a[:, c], fill[k]])
+    return p if fp64 else round_to_f32(p)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_move_edge_cases_match_oracle(fp64):
+    """One step from particles placed on the edges of the cell update: an
+    offset that rounds to exactly 1 after a small negative move, a landing on
+    exactly 1.0, exact corner crossings, no motion along an axis, starts on
+    the lower edges, at tile borders and across the periodic seam; zero
+    fields, so every displacement is the one chosen."""
+    w = Workload("edges", 40, 36, 4.0, 3.6, 0.07, 1,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2))], filter_passes=1)
+    rng = np.random.default_rng(77)
+    p = edge_particles(w, rng, fp64)
+    f = np.zeros((6, w.ny, w.nx))
+    sim, o = setup_pair(w, [p], f, fp64=fp64)
+    step_both(sim, o)
+    compare_state(sim, o, w, fp64, "move edges")
+    assert sim.status() == 0
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_gather_ties_and_cell_corners_match_oracle(fp64):
+    """Particles at offsets 1/2 (where each staggered component's bilinear
+    weight switches between its two neighbouring grid points: both give the
+    same value), on cell corners and just below 1, in random fields."""
+    w = Workload("ties", 40, 36, 4.0, 3.6, 0.07, 1,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2))], filter_passes=1)
+    rng = np.random.default_rng(78)
+    offs = np.array([0.5, 0.0, 1.0 - 2.0 ** -24, 0.25, 0.75])
+    ox, oy = np.meshgrid(offs, offs)
+    n_cell = 60
+    ix = rng.integers(0, w.nx, n_cell)
+    iy = rng.integers(0, w.ny, n_cell)
+    m = ox.size
+    p = dict(ix=np.repeat(ix, m).astype(np.int32), iy=np.repeat(iy, m).astype(np.int32),
+             x=np.tile(ox.ravel(), n_cell), y=np.tile(oy.ravel(), n_cell),
+             ux=0.3 * rng.standard_normal(m * n_cell), uy=0.3 * rng.standard_normal(m * n_cell),
+             uz=0.3 * rng.standard_normal(m * n_cell))
+    if not fp64:
+        p = round_to_f32(p)
+    f = (0.2 * rng.standard_normal((6, w.ny, w.nx))).astype(np.float32).astype(np.float64)
+    sim, o = setup_pair(w, [p], f, fp64=fp64)
+    step_both(sim, o)
+    compare_state(sim, o, w, fp64, "gather ties")

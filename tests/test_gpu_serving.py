@@ -118,3 +118,56 @@ def test_serving_batched_equals_one_at_a_time_and_respects_budget():
     r = serve([(0.0, small[1], 5), (0.0, big[1], 5)], budget, batched=True, chunk_steps=5)
     assert r["results"][0]["status"] == 0
     assert r["results"][1]["status"] == PIC_E_NOMEM
+
+
+def _serving_like(seed):
+    """Members of the serving stream's kind at its sizes: up to 512^2 cells
+    and 64 particles per cell, thermal and two-stream."""
+    return [
+        Workload("twostream_512x512_ppc64", 512, 512, 51.2, 51.2, 0.07, 10,
+                 [SpeciesSpec(-1.0, 0.5, ppc=(8, 8), uth=(0.05,) * 3, ufl=(0.35, 0, 0)),
+                  SpeciesSpec(-1.0, 0.5, ppc=(8, 8), uth=(0.05,) * 3, ufl=(-0.35, 0, 0))],
+                 seed=seed),
+        Workload("thermal_128x128_ppc4", 128, 128, 12.8, 12.8, 0.07, 10,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.2,) * 3)], seed=seed + 1),
+        Workload("thermal_256x256_ppc16", 256, 256, 25.6, 25.6, 0.07, 10,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(4, 4), uth=(0.01,) * 3)], seed=seed + 2),
+        Workload("twostream_64x64_ppc16", 64, 64, 6.4, 6.4, 0.07, 10,
+                 [SpeciesSpec(-1.0, 0.5, ppc=(4, 4), uth=(0.12,) * 3, ufl=(0.5, 0, 0)),
+                  SpeciesSpec(-1.0, 0.5, ppc=(4, 4), uth=(0.12,) * 3, ufl=(-0.5, 0, 0))],
+                 seed=seed + 3),
+    ]
+
+
+@pytest.mark.parametrize("halos", ["shared", "mixed"])
+def test_batched_members_match_the_oracle(halos):
+    """Heterogeneous simulations of the serving stream's kind stepped through
+    pic_batch_step (10 steps from their own loads), then one more batched
+    step compared, member by member, with an oracle that holds that member's
+    state: every component of J, the filtered J, E and B element by element,
+    and every particle paired one to one.  'shared': one filter halo for the
+    whole batch (the streaming field kernels over work lists); 'mixed':
+    filter halos 1, 2 and 3 (the tile-form field kernels)."""
+    import os
+    from parity_util import compare_state, oracle_mirror
+    ws = _serving_like(0x5EED7000 if halos == "shared" else 0x5EED7100)
+    if halos == "mixed":
+        ws[1].filter_passes, ws[1].filter_compensate = 1, True
+        ws[2].filter_passes = 3
+    sims = [Simulation(w) for w in ws]
+    ntiles = sum(s.layout()["ntx"] * s.layout()["nty"] for s in sims)
+    b = Batch(len(sims), ntiles)
+    b.step(sims, 10)
+    mirrors = []
+    for s, w in zip(sims, ws):
+        om = oracle_mirror(s, w)
+        om.set_threads(min(16, os.cpu_count() or 1))
+        mirrors.append(om)
+    b.step(sims, 1)
+    torch.cuda.synchronize()
+    for s, w, om in zip(sims, ws, mirrors):
+        om.step(1)
+        assert s.energy()["step"] == 11 and s.status() == 0
+        compare_state(s, om, w, False, "batched " + w.name)
+        om.close()
+    b.close()

@@ -202,3 +202,60 @@ def test_every_leaver_is_taken_by_exactly_one_tile(ntx, nty):
             assert len(takers) == 1 and takers[0][0] == dest, (a, dtx, dty, takers)
     assert sorted(dir_index(x, y) for x, y in itertools.product((-1, 0, 1), repeat=2)
                   if (x, y) != (0, 0)) == list(range(8))
+
+
+# ---------------------------------------------------------------------------
+# the commutative deposit (paper Sec. 3.2): tiles of one checkerboard colour
+# add their blocks straight into J in the same launch, so their blocks must
+# not share a cell
+# ---------------------------------------------------------------------------
+def colour_overlaps(nx, ny):
+    """Cells reached twice by the blocks of one colour: by two tiles, or by two
+    entries of one tile's block (a block wider than the period)."""
+    tx_, ty_ = tiles(nx), tiles(ny)
+    bad = []
+    for colour in range(4):
+        seen = {}
+        for b, h in ty_:
+            if b % 2 != colour >> 1:
+                continue
+            for a, w in tx_:
+                if a % 2 != colour & 1:
+                    continue
+                for py in range(-1, h + 2):
+                    for px in range(-1, w + 2):
+                        cell = ((TX * a + px) % nx, (TY * b + py) % ny)
+                        if cell in seen:
+                            bad.append((colour, cell, seen[cell], (a, b, px, py)))
+                        seen[cell] = (a, b, px, py)
+    return bad
+
+
+def test_commutative_colours_never_share_a_cell_where_the_library_accepts_the_grid():
+    import ctypes as C
+    import os
+    from inputs import thermal64
+    from paper_2106_12485_amd import build, pic
+    lib_path = os.path.join(os.path.dirname(__file__), "..", "paper_2106_12485_amd",
+                            "libpic.so")
+    if not os.path.exists(lib_path):
+        build.build(force=False)
+    L = pic.lib()
+    accepted = rejected = 0
+    for nx in range(2, 100):
+        for ny in (2, 3, 18, 19, 32, 34, 35, 50, 64):
+            c = pic.make_cfg(thermal64(), deposit="commutative")
+            c.nx, c.ny, c.lx, c.ly = nx, ny, 0.1 * nx, 0.1 * ny
+            ok = L.pic_mem_bytes(C.byref(c)) > 0
+            even = ((nx + 15) // 16) % 2 == 0 and ((ny + 15) // 16) % 2 == 0
+            if not even or nx % 16 == 1 or ny % 16 == 1:
+                assert not ok, (nx, ny)
+                continue
+            overl = colour_overlaps(nx, ny)
+            # accepted exactly where no two same-colour blocks meet
+            assert ok == (not overl), (nx, ny, overl[:3])
+            accepted += ok
+            rejected += not ok
+    assert accepted > 50 and rejected > 5
+    # the two grids with a 2-cell last tile that overlapped before they were refused
+    assert colour_overlaps(50, 32) and colour_overlaps(18, 20)

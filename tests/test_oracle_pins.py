@@ -672,6 +672,55 @@ def test_laser_polarisation_amplitude_and_propagation():
     assert abs(s.energy()["total"] / W0 - 1) < 1e-2
 
 
+def test_laser_focuses_to_its_waist_with_the_paraxial_phase():
+    """The initial laser, propagated by the oracle's own vacuum Yee solver,
+    behaves as the 2D Gaussian beam it claims to be.  A tight beam (W0 = 1,
+    w0 = 10, Rayleigh length zR = w0 W0^2 / 2 = 5) starts 8 units before its
+    focus, where the wavefront curvature (w0 r^2 / 2R) and the Gouy term
+    (-atan(z/zR)/2) are large, and travels 8 units:
+      - its transverse width, 2 sqrt(<y^2>) of the energy density, starts at
+        sqrt(<w(z)^2>) = 1.887 and shrinks to W0 at the focus; with the
+        curvature's sign flipped the beam would diverge to 3.2;
+      - the on-axis amplitude at the focus reaches a0 w0: the 2D beam's
+        sqrt(W0/w) amplitude factor (a 3D-style W0/w would give 0.73 a0 w0);
+      - the on-axis carrier phase at the focus is the plane wave's, up to the
+        Yee scheme's phase lag (k - w(k)) T; a Gouy term of the wrong sign or
+        without the 1/2 would leave the phase 1.0 rad off.
+    The beam is only marginally paraxial (divergence 2/(w0 W0) = 0.2 rad), so
+    width and amplitude are held to 6%."""
+    nx, ny, lx, ly, dt = 1152, 150, 24.0, 12.0, 0.018
+    dx, dy = lx / nx, ly / ny
+    a0, w0, W0, fwhm, xc, focus = 0.1, 10.0, 1.0, 1.0, 6.0, 14.0
+    axis = ly / 2
+    s = OracleSim(nx, ny, lx, ly, dt, window=False, filter_passes=0)
+    s.set_threads(min(8, os.cpu_count() or 1))
+    s.add_laser(a0, w0, W0, fwhm, xc, focus, axis, math.pi / 2)
+    y = np.arange(ny) * dy - axis
+
+    def width(f):
+        # energy density of the transverse components (Ey Ez By Bz)
+        dens = (f[[1, 2, 4, 5]] ** 2).sum(axis=(0, 2))
+        return 2 * math.sqrt((dens * y * y).sum() / dens.sum())
+
+    zr = 0.5 * w0 * W0 ** 2
+    var_z = fwhm ** 2 / (8 * math.log(2))  # variance of z under the intensity envelope
+    f0 = s.get_fields()
+    assert abs(width(f0) / (W0 * math.sqrt(1 + (64 + var_z) / zr ** 2)) - 1) < 0.01
+    n = int(round(8.0 / dt))
+    for _ in range(n):
+        s.yee()
+    T = n * dt
+    f1 = s.get_fields()
+    assert abs(width(f1) / W0 - 1) < 0.06, width(f1)
+    ez = f1[2, int(round(axis / dy)), :]
+    assert abs(np.abs(ez).max() / (a0 * w0) - 1) < 0.06
+    x = np.arange(nx) * dx
+    env = np.exp(-2 * math.log(2) * (x - xc - T) ** 2 / fwhm ** 2)
+    phase = np.angle((ez * env * np.exp(-1j * w0 * (x - xc - T))).sum())
+    lag = (w0 - 2 / dt * math.asin(dt / dx * math.sin(w0 * dx / 2))) * T
+    assert abs(phase - lag) < 0.15, (phase, lag)
+
+
 def test_moving_window_equals_shifted_periodic_box_inside_domain_of_dependence():
     # In window cells, the zero fields beyond the left edge reach at most one
     # cell per step to the right (E reads B one cell back); those beyond the
