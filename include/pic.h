@@ -152,52 +152,88 @@ typedef struct {
     int status;               /* device error state, as pic_status() */
 } pic_diag;
 
-/* Bytes of device arena that pic_init needs for this configuration, or 0 if
- * the configuration is invalid (pic_last_error() says why). */
+/* Device memory one simulation needs (the paper's per-region particle and
+ * current buffers of the spatial decomposition, Sec. 3.2, laid out as GPU
+ * tiles): the bytes of arena that pic_init will sub-allocate for `cfg`.
+ * Used for admission by HBM budget.  cfg is read only.  Returns 0 if the
+ * configuration is invalid (pic_last_error() says why); never touches the
+ * GPU. */
 size_t pic_mem_bytes(const pic_cfg *cfg);
 
-/* Validate cfg, lay the simulation out in `arena` (device memory, at least
- * pic_mem_bytes(cfg) bytes, 256-byte aligned, owned by the caller and kept
- * alive until pic_free), zero it, write the laser fields and load the
- * species (cfg->load).  Returns PIC_E_CFL if dt breaks the Courant limit,
- * PIC_E_NOMEM if the arena is too small, PIC_E_CAPACITY if the initial load
- * does not fit.  Synchronises `stream`.  On success *out owns host state. */
+/* Set a simulation up as the paper's evaluation runs start (Sec. 4.1):
+ * fields zero except the initial laser, species loaded on their sub-cell
+ * lattice with their density profile and momentum distribution, immobile
+ * neutralising ions implied by the t = 0 charge.  The time step must satisfy
+ * the Courant limit of the Yee scheme of Sec. 2.2 stage 4.
+ *   cfg    host struct, read only during the call;
+ *   arena  device memory of at least arena_bytes >= pic_mem_bytes(cfg)
+ *          bytes, 256-byte aligned, owned by the caller and kept alive until
+ *          pic_free; the library zeroes it and keeps every device array in it;
+ *   out    receives a handle owning host-side state only.
+ * Errors: PIC_E_ARG (invalid cfg or NULL pointer), PIC_E_CFL (Courant limit),
+ * PIC_E_NOMEM (arena too small), PIC_E_CAPACITY (initial load does not fit
+ * its tiles), PIC_E_HIP.  On error *out is untouched and nothing is held.
+ * Synchronises `stream`. */
 int pic_init(const pic_cfg *cfg, void *arena, size_t arena_bytes, void *stream,
              pic_sim **out);
 
-/* Stages 1-3 plus the particle hand-off between tiles (hot-path rows a1-a4):
- * interpolate E^n, B^n to every particle, Boris push to u^{n+1/2}, move, and
- * deposit the Villasenor-Buneman current of the move into per-tile blocks;
- * then append the particles that left their tile to the tile they entered.
- * Asynchronous on stream. */
+/* Stages 1-3 of the cycle (Sec. 2.2, Fig. 1) with the particle transfer
+ * between neighbouring regions of Sec. 3.2: interpolate E^n, B^n bilinearly
+ * to every particle (stage 1), Boris push to u^{n+1/2} and move (stage 2),
+ * deposit the Villasenor-Buneman current of the move into the per-tile
+ * current blocks (stage 3, the regions' local buffers with ghost cells), and
+ * hand each particle that left its tile to the tile it entered.  Work is
+ * enqueued on `stream` and not waited for.  Errors: PIC_E_ARG (NULL handle),
+ * PIC_E_HIP (launch failed); a tile or outbox that overflows sets the device
+ * error reported by pic_status. */
 int pic_deposit(pic_sim *sim, void *stream);
 
-/* Rows a5-a8: fold the per-tile current blocks into the global current
- * (periodic wrap, or drop beyond the moving window), apply the filter, advance
- * E, B by one Yee step (B half, E full, B half) and, with the moving window,
- * shift the window by one cell once the light front has crossed the next
+/* The rest of the step: the reduction of the regions' ghost-cell currents
+ * (Sec. 3.2; periodic wrap, or dropped beyond the moving window), the
+ * binomial digital filter of stage 3 (Sec. 2.2; with the compensator of the
+ * laser-wakefield runs, Sec. 4.1), one Yee FDTD advance of E and B (stage 4:
+ * B half step, E full step, B half step) and, with the moving window of
+ * Sec. 4.1, a shift by one cell once the light front has crossed the next
  * cell boundary (iter*dt >= (nshift+1)*dx in double), removing the particles
- * of the column that leaves and loading the column that enters.
- * Asynchronous on stream. */
+ * of the column that leaves and loading the column that enters.  Must follow
+ * pic_deposit of the same step.  Enqueued on `stream`, not waited for.
+ * Errors: PIC_E_ARG (NULL handle), PIC_E_HIP. */
 int pic_field_advance(pic_sim *sim, void *stream);
 
-/* nsteps times (pic_deposit; pic_field_advance).  Between steps the leavers
- * of a push stay in their outboxes and the next push takes them from there
- * (calls that read particles append them first).  The steps are replayed
- * from HIP graphs captured on first use: one of 8 steps while 8 or more
- * remain, then one of a single step.  Asynchronous on stream. */
+/* nsteps iterations of the main simulation loop (Sec. 2.2, Fig. 1), each
+ * pic_deposit then pic_field_advance.  Between steps the leavers of a push
+ * stay in their outboxes and the next push takes them from there (calls that
+ * read particles append them first).  The steps are replayed from HIP graphs
+ * captured on first use: one of 8 steps while 8 or more remain, then one of a
+ * single step.  nsteps >= 0.  Enqueued on `stream`, not waited for.
+ * Errors: PIC_E_ARG (NULL handle, nsteps < 0), PIC_E_HIP. */
 int pic_step(pic_sim *sim, int nsteps, void *stream);
 
-/* FP64 diagnostics of the current state (see pic_diag).  Synchronises. */
+/* FP64 diagnostics of the current state (see pic_diag): the field and
+ * kinetic energies the paper's validation compares between versions of the
+ * code (Sec. 4.2), total charge, and the Gauss and continuity residuals that
+ * the exact charge-conserving deposit of Sec. 2.2 stage 3 keeps at round-off.
+ * out is a caller-owned host struct, filled on success.  Errors: PIC_E_ARG,
+ * PIC_E_HIP.  Synchronises `stream`. */
 int pic_energy(pic_sim *sim, pic_diag *out, void *stream);
 
-/* Device error state accumulated so far: PIC_OK or PIC_E_CAPACITY (a tile or
- * an outbox overflowed; the excess particles were dropped and the run is no
+/* Device error state accumulated so far (no paper passage: a check of the
+ * tile capacities of this layout): PIC_OK or PIC_E_CAPACITY (a tile or an
+ * outbox overflowed; the excess particles were dropped and the run is no
  * longer valid).  Synchronises. */
 int pic_status(pic_sim *sim, void *stream);
 
-/* Release the host state.  The arena stays the caller's. */
+/* Release the host state of a handle (NULL is ignored).  Waits for no
+ * device work: the caller must not free the arena while work on it is in
+ * flight.  The arena stays the caller's. */
 int pic_free(pic_sim *sim);
+
+/* ---------------------------------------------------------------------
+ * State input and output (tests, checkpoints, serving).  No paper passage
+ * defines these; they move the state of Sec. 2.2 (particles, E, B, J)
+ * between host arrays and the device, converting to and from FP64.
+ * Host arrays are caller-owned and only touched during the call.
+ * ------------------------------------------------------------------- */
 
 /* Replace all particles of species sp with n particles given as host arrays
  * (ix in [0, nx), iy in [0, ny), x, y in [0, 1)); values are rounded to the
@@ -245,9 +281,10 @@ int pic_set_time(pic_sim *sim, long long iter, int nshift, void *stream);
  * the Yee launch folds), 3 filter (only the requests of pic_get_current:
  * the step filters inside the Yee launch), 4 current filter + Yee (and the
  * fold, where it has no launch of its own) and the step end (field buffer
- * flip, step count), 5 moving-window shift.
+ * flip, step count), 5 moving-window shift, 6 the push's work order (tiles
+ * by decreasing particle count, rewritten every 8 steps).
  * Synchronises. */
-#define PIC_NK 6
+#define PIC_NK 7
 int pic_timing(pic_sim *sim, int enable, void *stream);
 int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void *stream);
 

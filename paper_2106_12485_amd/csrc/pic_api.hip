@@ -74,7 +74,7 @@ struct Layout {
     size_t rs;  // bytes of the working precision
     size_t plane;  // elements of one storage plane
     size_t off_state, off_F, off_J, off_Jf, off_rho, off_rho_f, off_rho_prev, off_g0, off_blk,
-        off_red, off_res;
+        off_red, off_res, off_order;
     size_t off_sp[MAX_SP];  // start of each species block
     size_t sp_bytes[MAX_SP];
     size_t total;
@@ -166,6 +166,7 @@ int layout(const pic_cfg *c, Layout *L)
     L->off_blk = take((size_t)L->ntiles * 3 * BP * (L->nsb > 1 ? L->nsb * 8 : L->rs));
     L->off_red = take(((size_t)NB_DIAG * 5 + (size_t)L->ntiles * MAX_SP) * 8);
     L->off_res = take(N_RED * 8);
+    L->off_order = take((size_t)L->ntiles * L->nsb * 4);
     const size_t obs = (size_t)L->ntiles * L->cap_out;
     for (int s = 0; s < c->n_species; ++s) {
         const size_t slots = (size_t)L->ntiles * L->cap[s];
@@ -243,6 +244,7 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->rho_prev = (R *)(a + L.off_rho_prev);
     d->g0 = (double *)(a + L.off_g0);
     d->blk = (R *)(a + L.off_blk);
+    d->order = (int *)(a + L.off_order);
     d->red = (double *)(a + L.off_red);
     d->res = (double *)(a + L.off_res);
     d->st = (DevState *)(a + L.off_state);
@@ -330,6 +332,7 @@ struct pic_sim {
     long long launches[PIC_NK];
     // diagnostics
     long long rho_prev_iter = -2;
+    long long pushes_enqueued = 0;  // directly launched pushes (work order cadence)
     DevState hs;  // host copy, valid after read_state
     unsigned long long uid = 0;  // unique per pic_init (handles may reuse addresses)
 };
@@ -406,11 +409,35 @@ int enqueue_settle(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool only_if_
     return timed(s, 1, st, [&] { return Launch<R>::settle(d, st, only_if_shift, unpend); });
 }
 
+// The push's work order (heaviest tiles first) is rewritten every
+// GRAPH_STEPS steps: particle counts move slowly, and the order only has to
+// be close.
+constexpr int GRAPH_STEPS = 8;
+
+// The push of one step, preceded by a new work order when `order` is set.
+template <typename R>
+int enqueue_push(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool order)
+{
+    if (order && !d.direct) {
+        const int rc = timed(s, 6, st, [&] { return Launch<R>::order(d, st); });
+        if (rc) return rc;
+    }
+    return timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
+}
+
+// a push launched directly (not from a graph): a new order every
+// GRAPH_STEPS of them
+template <typename R>
+int enqueue_push_direct(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+{
+    return enqueue_push(s, d, st, s->pushes_enqueued++ % GRAPH_STEPS == 0);
+}
+
 // a1-a4: push + deposit; the leavers are then appended to their new tiles
 template <typename R>
 int enqueue_deposit(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
-    int rc = timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
+    int rc = enqueue_push_direct(s, d, st);
     if (rc) return rc;
     return enqueue_settle(s, d, st);
 }
@@ -443,9 +470,9 @@ int enqueue_field_advance(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 // One step of pic_step: the next push takes the pending leavers directly
 // from the outboxes, so no hand-off launch is needed between steps.
 template <typename R>
-int enqueue_step(pic_sim *s, const SimDev<R> &d, hipStream_t st)
+int enqueue_step(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool order)
 {
-    int rc = timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
+    int rc = enqueue_push(s, d, st, order);
     if (rc) return rc;
     return enqueue_field_advance(s, d, st);
 }
@@ -480,6 +507,15 @@ int do_init(pic_sim *s, const SimDev<R> &d, hipStream_t st)
     const pic_cfg &c = s->cfg;
     const Layout &L = s->L;
     HIPCHK(hipMemsetAsync(s->arena, 0, L.total, st));
+    {
+        // the push's first work order: every item once (the field launch of
+        // each step rewrites it, heaviest first)
+        std::vector<int> ord((size_t)L.ntiles * L.nsb);
+        for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+        HIPCHK(hipMemcpyAsync(d.order, ord.data(), ord.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     if (c.laser.on) {
         std::vector<R> h(L.plane * 6, R(0));
         const pic_laser_cfg &l = c.laser;
@@ -704,10 +740,10 @@ int do_planes(pic_sim *s, R *const *dev, int np, double *host, bool to_dev, hipS
     return PIC_OK;
 }
 
-// Steps replayed from captured graphs: one of GRAPH_STEPS steps while that
-// many remain, then one-step graphs (fewer graph launches, and no gap
-// between the steps inside one graph).
-constexpr int GRAPH_STEPS = 8;
+// Steps replayed from captured graphs: one of GRAPH_STEPS steps (the first
+// of them rewriting the push's work order) while that many remain, then
+// one-step graphs (fewer graph launches, and no gap between the steps inside
+// one graph).
 
 template <typename R>
 int capture_steps(pic_sim *s, const SimDev<R> &d, int k, hipGraph_t *graph, hipGraphExec_t *exec)
@@ -715,7 +751,8 @@ int capture_steps(pic_sim *s, const SimDev<R> &d, int k, hipGraph_t *graph, hipG
     if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
     int rc = PIC_OK;
-    for (int n = 0; n < k && rc == PIC_OK; ++n) rc = enqueue_step(s, d, s->cap_stream);
+    for (int n = 0; n < k && rc == PIC_OK; ++n)
+        rc = enqueue_step(s, d, s->cap_stream, n == 0 && k == GRAPH_STEPS);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
     if (rc) {
@@ -734,7 +771,7 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
 {
     if (s->timing) {
         for (int n = 0; n < nsteps; ++n) {
-            int rc = enqueue_step(s, d, st);
+            int rc = enqueue_step(s, d, st, s->pushes_enqueued++ % GRAPH_STEPS == 0);
             if (rc) return rc;
         }
         return PIC_OK;

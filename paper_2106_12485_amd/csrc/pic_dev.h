@@ -108,6 +108,8 @@ struct SimDev {
     int push_bt;      // threads per single-simulation push block: NTP or NTP_BIG
     int nsb;          // push blocks per tile: 1, or one per species (blk then holds
                       // nsb slices of 64-bit sums per tile)
+    int *order;       // work items of the single-simulation push (ntiles * nsb):
+                      // block b takes order[b]; heaviest first
     int npass, compensate;
     int direct;       // 1: colour-phased deposit straight into J (no fold)
     R dx, dy, dt;
@@ -149,12 +151,14 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
 // Current and charge are summed in LDS as 64-bit fixed point: integer LDS
 // atomics run at the rate of plain LDS traffic on CDNA, floating-point ones
 // do not, and integer sums do not depend on the order of the additions, so
-// the result is bitwise reproducible.  A term v enters as floor(v * 2^e).
+// the result is bitwise reproducible.  A term v enters as v * 2^e made an
+// integer (FP32: floor; FP64: nearest).
 // Callers pass y = v * jq with the power-of-two scale jq folded into their
 // per-species prefactors, so y rounds exactly as v would.  FP32 (jq =
 // 2^(e-32)): the high word is floor(y) and the low word fract(y) * 2^32, both
 // exact; the hardware fract is clamped below 1, which moves a negative term
-// smaller than 2^-25 in y by less than 2^-24 in y.  FP64 (jq = 2^e): floor(y).
+// smaller than 2^-25 in y by less than 2^-24 in y.  FP64 (jq = 2^e): y rounded
+// to the nearest integer.
 __device__ __forceinline__ void lds_acc(unsigned long long *p, float y)
 {
     int hi;  // floor(y) converted in one instruction
@@ -166,7 +170,10 @@ __device__ __forceinline__ void lds_acc(unsigned long long *p, float y)
 
 __device__ __forceinline__ void lds_acc(unsigned long long *p, double y)
 {
-    const long long q = (long long)floor(y);
+    // nearest integer: a floor would lower every term by half a unit on
+    // average, and an entry that sums thousands of terms would drift by as
+    // many half-units
+    const long long q = (long long)rint(y);
     __hip_atomic_fetch_add(p, (unsigned long long)q, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -254,6 +261,8 @@ template <typename R> inline bool folds_in_yee(const SimDev<R> &d)
 
 template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
+    // rewrite the push's work order, heaviest items first
+    static hipError_t order(const SimDev<R> &d, hipStream_t s);
     // only_if_shift: skip unless the last step shifted the moving window;
     // unpend = false leaves clearing the pending flag to the window launch
     static hipError_t settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift = false,

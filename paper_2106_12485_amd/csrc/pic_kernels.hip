@@ -6,6 +6,8 @@
 // precision R (float for the production path, double for the FP64 path).
 #include "pic_dev.h"
 
+#include <algorithm>
+
 namespace pic {
 
 // ---------------------------------------------------------------------------
@@ -185,26 +187,118 @@ __device__ __forceinline__ void neighbour_runs(const SimDev<R> &d, const SpDev<R
 }
 
 // ---------------------------------------------------------------------------
-// rows a1-a4: one block per tile and step.  Every particle of the tile
-// (buffer ppar) and every leaver of the previous push that came to this tile
-// (outbox opar, if pending) is interpolated, pushed and deposited; particles
-// that stay are written compacted to buffer ppar ^ 1, one contiguous run per
-// wavefront, and the ones that leave go to outbox opar ^ 1 with their
-// direction.  Particles leaving the moving window are dropped.
+// rows a1-a4: the advance of one tile (the paper's region, Sec. 3.2) and
+// step.  Every particle of the tile (buffer ppar) and every leaver of the
+// previous push that came to this tile (outbox opar, if pending) is
+// interpolated, pushed and deposited; particles that stay are written
+// compacted to buffer ppar ^ 1, one contiguous run per wavefront, and the ones
+// that leave go to outbox opar ^ 1 with their direction.  Particles leaving
+// the moving window are dropped.
+//
+// A block first gathers the arrivals of each species into a list in LDS (the
+// outbox slots of the neighbours' leavers whose direction points at this
+// tile), then runs one stream per species over its own particles followed by
+// that list, so the arrivals fill the last, partial batch of the tile's own
+// particles instead of taking batches of their own.
 // ---------------------------------------------------------------------------
-// g: with d.nsb > 1 species blocks per tile, this block pushes species g only
-// and leaves its current block as exact 64-bit sums in slice g of the tile
-// (the fold adds the slices as integers before converting, so the result is
-// the same bits as one block pushing every species).
-template <int BT, bool DIRECT, typename R>
-__device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const int g = 0,
-                                          const int nsb = 1)
+// Entries of the arrival list per push block (all species of the block share
+// it): 16 KB of LDS beside the 17 KB field and current blocks leaves room for
+// four 512-thread blocks per CU; 1024-thread blocks run two per CU.
+template <int BT> struct ArrivalCap { static constexpr int n = BT >= 1024 ? 12288 : 4096; };
+
+template <typename R, int LCAP>
+struct PushShared {
+    R sf[6 * BP];                 // E, B of the tile block
+    unsigned long long sj[3 * BP];  // Jx, Jy, Jz of the tile block (fixed point)
+    int arr[LCAP];                // arrivals: outbox slot of each
+    int n_arr[MAX_SP];            // arrivals found per species
+    int n_out[MAX_SP];            // stayers written per species
+    int n_ob[MAX_SP];             // leavers written per species
+    int item;                     // work item of a persistent block
+};
+
+// Zero the per-species counters (before the barrier that precedes a tile).
+template <typename R, int LCAP>
+__device__ __forceinline__ void push_counters_zero(PushShared<R, LCAP> &sh)
 {
-    __shared__ R sf[6 * BP];
-    __shared__ unsigned long long sj[3 * BP];
-    __shared__ int s_nb[N_DIR], s_pre[N_DIR + 1];
-    __shared__ unsigned char s_want[N_DIR];
-    __shared__ int s_out, s_nob;
+    if (threadIdx.x < MAX_SP) {
+        sh.n_arr[threadIdx.x] = 0;
+        sh.n_out[threadIdx.x] = 0;
+        sh.n_ob[threadIdx.x] = 0;
+    }
+}
+
+// Append to `list` (capacity lcap; the count in *n) the outbox-ob slots of
+// species P's leavers that the 8 neighbours of tile (tx, ty) sent to it.  All
+// threads of the block take part; no barrier.  Every wavefront reads the 8
+// outbox lengths itself (lanes 0..7) and forms their prefix with lane
+// shuffles.  A leaver of neighbour k (k9 = k or k + 1, skipping the centre,
+// offset (k9 % 3 - 1, k9 / 3 - 1)) came to this tile if its direction is
+// dir_index of the opposite offset, which is 7 - k.
+template <int BT, typename R>
+__device__ __forceinline__ void gather_arrivals(const SimDev<R> &d, const SpDev<R> &P, int tx,
+                                                int ty, int ob, int *list, int lcap, int *n)
+{
+    const int lane = threadIdx.x & 63;
+    int len = 0;
+    if (lane < N_DIR) {
+        const int k9 = lane < 4 ? lane : lane + 1;
+        const int nb = wrapi(tx + k9 % 3 - 1, d.ntx) + wrapi(ty + k9 / 3 - 1, d.nty) * d.ntx;
+        len = glob(P.ob_count[ob])[nb];
+    }
+    int inc = len;  // inclusive prefix over lanes 0..7
+#pragma unroll
+    for (int o = 1; o < N_DIR; o <<= 1) {
+        const int v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    int pre[N_DIR + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int k = 0; k < N_DIR; ++k) pre[k + 1] = __builtin_amdgcn_readlane(inc, k);
+    const int total = pre[N_DIR];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const gptr<const unsigned char> dirs = glob<const unsigned char>(P.ob_dir[ob]);
+    for (int e0 = 0; e0 < total; e0 += BT) {
+        const int e = e0 + (int)threadIdx.x;
+        bool take = false;
+        int o = 0;
+        if (e < total) {
+            int k = 0, start = 0;
+#pragma unroll
+            for (int j = 1; j < N_DIR; ++j) {
+                const bool past = e >= pre[j];
+                k += past ? 1 : 0;
+                start = past ? pre[j] : start;
+            }
+            const int k9 = k < 4 ? k : k + 1;
+            const int nb = wrapi(tx + k9 % 3 - 1, d.ntx) + wrapi(ty + k9 / 3 - 1, d.nty) * d.ntx;
+            o = nb * d.cap_out + (e - start);
+            take = dirs[o] == (unsigned char)(N_DIR - 1 - k);
+        }
+        const unsigned long long m = __ballot(take);
+        if (m) {
+            int off = 0;
+            if (lane == 0) off = atomicAdd(n, (int)__popcll(m));
+            off = __builtin_amdgcn_readfirstlane(off);
+            const int q = off + (int)__popcll(m & below);
+            if (take && q < lcap) list[q] = o;
+        }
+    }
+}
+
+// One tile (t) of one push: g selects the species when d.nsb > 1 species
+// blocks share a tile (this block then pushes species g only and leaves its
+// current block as exact 64-bit sums in slice g of the tile; the fold adds
+// the slices as integers before converting, so the result is the same bits as
+// one block pushing every species).  Needs the counters of `sh` zeroed and a
+// barrier before; ends without a barrier, with the counters zeroed again.
+template <int BT, bool DIRECT, typename R, int LCAP>
+__device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const int g,
+                                          const int nsb, PushShared<R, LCAP> &sh)
+{
+    R *const sf = sh.sf;
+    unsigned long long *const sj = sh.sj;
     const int tx = t % d.ntx, ty = t / d.ntx;
     const int x0 = tx * TX, y0 = ty * TY;
     const int w = min(TX, d.nxs - x0), h = min(TY, d.ny - y0);
@@ -212,29 +306,27 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const
     const int par = st->parity, origin = st->origin;
     const int pp = st->ppar, ob = st->opar;
     const bool pend = st->pend != 0;
+    const int s0 = nsb > 1 ? g : 0, s1 = nsb > 1 ? g + 1 : d.nsp;
+    const int lcap = LCAP / max(s1 - s0, 1);
     load_tile_fields<BT>(d, par, x0, y0, w, h, sf, sj);
+    if (pend)
+        for (int s = s0; s < s1; ++s)
+            gather_arrivals<BT>(d, d.sp[s], tx, ty, ob, sh.arr + (s - s0) * lcap, lcap,
+                                &sh.n_arr[s]);
+    __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     const R jq = d.jq;
     const size_t obase = (size_t)t * d.cap_out;
-    const int s0 = nsb > 1 ? g : 0, s1 = nsb > 1 ? g + 1 : d.nsp;
     for (int s = s0; s < s1; ++s) {
         const SpDev<R> &P = d.sp[s];
-        neighbour_runs(d, P, t, ob, pend, s_nb, s_want, s_pre + 1);
-        if (threadIdx.x == 0) {
-            s_out = 0;
-            s_nob = 0;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_pre[0] = 0;
-            for (int k = 0; k < N_DIR; ++k) s_pre[k + 1] += s_pre[k];
-        }
-        __syncthreads();
         const PartBuf<R> &bi = P.pb[pp];
         const PartBuf<R> &bo = P.pb[pp ^ 1];
         const unsigned n_own = (unsigned)glob(bi.count)[t];
+        const int n_found = sh.n_arr[s];
+        const unsigned n_tot = n_own + (unsigned)min(n_found, lcap);
+        const int *const list = sh.arr + (s - s0) * lcap;
         const size_t base = (size_t)t * P.cap;
         // tile-uniform base pointers, indexed with 32-bit offsets
         const int *const ic = bi.cell + base;
@@ -313,7 +405,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const
             const unsigned long long ms = __ballot(stay);
             if (ms) {
                 int off = 0;
-                if (lane == 0) off = atomicAdd(&s_out, (int)__popcll(ms));
+                if (lane == 0) off = atomicAdd(&sh.n_out[s], (int)__popcll(ms));
                 off = __builtin_amdgcn_readfirstlane(off);
                 if (stay) {
                     const unsigned q = (unsigned)(off + (int)__popcll(ms & below));
@@ -335,7 +427,7 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const
             const unsigned long long ml = __ballot(send);
             if (ml) {
                 int off = 0;
-                if (lane == 0) off = atomicAdd(&s_nob, (int)__popcll(ml));
+                if (lane == 0) off = atomicAdd(&sh.n_ob[s], (int)__popcll(ml));
                 off = __builtin_amdgcn_readfirstlane(off);
                 if (send) {
                     const int slot = off + (int)__popcll(ml & below);
@@ -355,64 +447,52 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const
                 }
             }
         };
-        // Own particles, read one batch ahead: the loads of batch k+1 are in
+        // Particle i of the stream: own particle i, or arrival i - n_own.
+        auto fetch = [&](unsigned i, int &c, R &x, R &y, R &ux, R &uy, R &uz) {
+            if (i < n_own) {
+                const unsigned o4 = i * 4u, oR = i * (unsigned)sizeof(R);
+                c = at(ic, o4);
+                x = at(ixp, oR);
+                y = at(iyp, oR);
+                ux = at(iux, oR);
+                uy = at(iuy, oR);
+                uz = at(iuz, oR);
+            } else if (i < n_tot) {
+                const size_t o = (size_t)list[i - n_own];
+                c = glob(P.ob_cell[ob])[o];
+                x = glob(P.ob_x[ob])[o];
+                y = glob(P.ob_y[ob])[o];
+                ux = glob(P.ob_ux[ob])[o];
+                uy = glob(P.ob_uy[ob])[o];
+                uz = glob(P.ob_uz[ob])[o];
+            }
+        };
+        // The stream, read one batch ahead: the loads of batch k+1 are in
         // flight while batch k is pushed and deposited.
         int nc = 0;
         R nxv = 0, nyv = 0, nux = 0, nuy = 0, nuz = 0;
-        if (threadIdx.x < n_own) {
-            const unsigned o4 = threadIdx.x * 4u, oR = threadIdx.x * (unsigned)sizeof(R);
-            nc = at(ic, o4);
-            nxv = at(ixp, oR);
-            nyv = at(iyp, oR);
-            nux = at(iux, oR);
-            nuy = at(iuy, oR);
-            nuz = at(iuz, oR);
-        }
-        for (unsigned p0 = 0; p0 < n_own; p0 += BT) {
+        fetch(threadIdx.x, nc, nxv, nyv, nux, nuy, nuz);
+        for (unsigned p0 = 0; p0 < n_tot; p0 += BT) {
             const unsigned p = p0 + threadIdx.x;
             const int cell = nc;
             const R x = nxv, y = nyv, ux = nux, uy = nuy, uz = nuz;
-            const unsigned pn = p + BT;
-            if (pn < n_own) {
-                const unsigned o4 = pn * 4u, oR = pn * (unsigned)sizeof(R);
-                nc = at(ic, o4);
-                nxv = at(ixp, oR);
-                nyv = at(iyp, oR);
-                nux = at(iux, oR);
-                nuy = at(iuy, oR);
-                nuz = at(iuz, oR);
-            }
-            advance(p < n_own, cell, x, y, ux, uy, uz);
+            fetch(p + BT, nc, nxv, nyv, nux, nuy, nuz);
+            advance(p < n_tot, cell, x, y, ux, uy, uz);
         }
-        // Leavers of the previous push from the 8 neighbours that moved here.
-        const unsigned n_in = (unsigned)s_pre[N_DIR];
-        for (unsigned e0 = 0; e0 < n_in; e0 += BT) {
-            const int e = (int)(e0 + threadIdx.x);
-            bool act = false;
-            int cell = 0;
-            R x = 0, y = 0, ux = 0, uy = 0, uz = 0;
-            if (e < (int)n_in) {
-                int k = 0;
-                while (k < N_DIR - 1 && e >= s_pre[k + 1]) ++k;
-                const size_t o = (size_t)s_nb[k] * d.cap_out + (e - s_pre[k]);
-                if (glob(P.ob_dir[ob])[o] == s_want[k]) {
-                    cell = glob(P.ob_cell[ob])[o];
-                    x = glob(P.ob_x[ob])[o];
-                    y = glob(P.ob_y[ob])[o];
-                    ux = glob(P.ob_ux[ob])[o];
-                    uy = glob(P.ob_uy[ob])[o];
-                    uz = glob(P.ob_uz[ob])[o];
-                    act = true;
-                }
-            }
-            advance(act, cell, x, y, ux, uy, uz);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            glob(bo.count)[t] = min(s_out, P.cap);
-            glob(P.ob_count[ob ^ 1])[t] = min(s_nob, d.cap_out);
-        }
-        __syncthreads();
+        if (threadIdx.x == 0 && n_found > lcap)
+            __hip_atomic_fetch_or(&glob(d.st)->err, ERR_CAPACITY, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    // counts of the tile, and the counters zeroed for the block's next tile
+    if ((int)threadIdx.x < s1 - s0) {
+        const int s = s0 + (int)threadIdx.x;
+        const SpDev<R> &P = d.sp[s];
+        glob(P.pb[pp ^ 1].count)[t] = min(sh.n_out[s], P.cap);
+        glob(P.ob_count[ob ^ 1])[t] = min(sh.n_ob[s], d.cap_out);
+        sh.n_arr[s] = 0;
+        sh.n_out[s] = 0;
+        sh.n_ob[s] = 0;
     }
     // one flush of the tile's current block per step
     const double jqi = d.jq_inv;
@@ -423,9 +503,9 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const
             const int c = k / BP, kk = k - c * BP;
             const int lx = kk % PX - 1, ly = kk / PX - 1;
             if (lx >= w + 2 || ly >= h + 2) continue;  // beyond a ragged tile's guards
-            const size_t g = (size_t)wrapi(x0 + lx, d.nxs) + (size_t)wrapi(y0 + ly, d.ny) * d.nxs;
+            const size_t gi = (size_t)wrapi(x0 + lx, d.nxs) + (size_t)wrapi(y0 + ly, d.ny) * d.nxs;
             const gptr<R> J = glob(d.J[c]);
-            J[g] = J[g] + (R)fx_value(sj[k], jqi);
+            J[gi] = J[gi] + (R)fx_value(sj[k], jqi);
         }
     } else if (nsb > 1) {
         const gptr<unsigned long long> out = glob(
@@ -435,6 +515,16 @@ __device__ __forceinline__ void push_body(const SimDev<R> &d, const int t, const
         const gptr<R> out = glob(d.blk + (size_t)t * 3 * BP);
         for (int k = threadIdx.x; k < 3 * BP; k += BT) out[k] = (R)fx_value(sj[k], jqi);
     }
+}
+
+// One tile per block (batched and colour-phased launches).
+template <int BT, bool DIRECT, typename R>
+__device__ __forceinline__ void push_body(const SimDev<R> &d, const int t)
+{
+    __shared__ PushShared<R, ArrivalCap<BT>::n> sh;
+    push_counters_zero(sh);
+    __syncthreads();
+    push_tile<BT, DIRECT>(d, t, 0, 1, sh);
 }
 
 // After each push: both buffers flip and its outbox is pending.
@@ -1180,6 +1270,60 @@ __device__ __forceinline__ void yee_s_body(const SimDev<R> &d, const int blk)
     }
 }
 
+// Work order of the push: its work items (tiles, or a tile's species
+// blocks) by decreasing particle count, in 64 buckets two per octave,
+// heaviest first.  Within a bucket the order is that of the atomic claims;
+// any order is a permutation of the items, which is all the push needs.
+// One block of NTO threads.
+constexpr int NTO = 1024;
+
+__device__ __forceinline__ int load_bucket(int n)
+{
+    // 2 floor(log2(n + 1)) + the next bit: 0 .. 63, monotone in n
+    const unsigned v = (unsigned)n + 1u;
+    const int e = 31 - __clz(v);
+    const int half = e > 0 ? (int)((v >> (e - 1)) & 1u) : 0;
+    return min(63, 2 * e + half);
+}
+
+template <typename R>
+__device__ __forceinline__ int item_slot(const SimDev<R> &d, int pp, int i)
+{
+    // bucket index of item i, heaviest first
+    const int t = i / d.nsb;
+    int n = 0;
+    if (d.nsb > 1)
+        n = glob(d.sp[i % d.nsb].pb[pp].count)[t];
+    else
+        for (int s = 0; s < d.nsp; ++s) n += glob(d.sp[s].pb[pp].count)[t];
+    return 63 - load_bucket(n);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
+{
+    __shared__ int hist[64];
+    const int pp = glob(d.st)->ppar, n = d.ntiles * d.nsb;
+    if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NTO) atomicAdd(&hist[item_slot(d, pp, i)], 1);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // exclusive prefix over the buckets (one wavefront)
+        const int v = hist[threadIdx.x];
+        int inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(inc, o, 64);
+            if ((int)threadIdx.x >= o) inc += u;
+        }
+        hist[threadIdx.x] = inc - v;
+    }
+    __syncthreads();
+    const gptr<int> order = glob(d.order);
+    for (int i = threadIdx.x; i < n; i += NTO) order[atomicAdd(&hist[item_slot(d, pp, i)], 1)] = i;
+}
+
 template <typename R, int RF>
 __global__ __launch_bounds__(64) void k_yee_s(SimDev<R> d)
 {
@@ -1703,13 +1847,24 @@ template <> struct PushWaves<double> { static constexpr int n = 4; };
 // Tiles that hold many particles (the Weibel run's 131,072) take blocks of
 // NTP_BIG threads: a tile's work then spreads over twice the wavefronts,
 // which shortens the launch most when the particles pile up in a few tiles.
+//
+// Block b takes work item d.order[b] (a tile, or a tile's species block).
+// Blocks are dispatched in about the order of their index, and the order
+// lists the items by decreasing particle count (k_order rewrites it every
+// 8 steps), so heavy tiles start first and the launch ends on light ones:
+// the GPU form of the paper's over-decomposition with dynamic distribution
+// of regions to workers (Sec. 3.2, 4.3), where a region that holds many
+// particles must not start last.
 template <typename R, int BT>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
 k_push_deposit(SimDev<R> d)
 {
-    // the species blocks of a tile are neighbours in the dispatch order
-    const int i = xcd_remap(blockIdx.x, gridDim.x), nsb = d.nsb;
-    push_body<BT, false>(d, i / nsb, i % nsb, nsb);
+    __shared__ PushShared<R, ArrivalCap<BT>::n> sh;
+    const int nsb = d.nsb;
+    const int i = __builtin_amdgcn_readfirstlane(glob(d.order)[blockIdx.x]);
+    push_counters_zero(sh);
+    __syncthreads();
+    push_tile<BT, false>(d, i / nsb, i % nsb, nsb, sh);
     if (last_block(&d.st->blocks_done)) push_end_body(d);
 }
 
@@ -1833,6 +1988,13 @@ hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
         hipLaunchKernelGGL((k_push_deposit<R, NTP_BIG>), grid, dim3(NTP_BIG), 0, s, d);
     else
         hipLaunchKernelGGL((k_push_deposit<R, NTP>), grid, dim3(NTP), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::order(const SimDev<R> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_order<R>, dim3(1), dim3(NTO), 0, s, d);
     return hipGetLastError();
 }
 

@@ -15,8 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 MAX_SPECIES = 4
-NK = 6
-KERNEL_NAMES = ("push_deposit", "settle", "fold", "filter", "yee", "window")
+NK = 7
+KERNEL_NAMES = ("push_deposit", "settle", "fold", "filter", "yee", "window", "order")
 
 PIC_OK, PIC_E_ARG, PIC_E_CFL, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
