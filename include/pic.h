@@ -323,6 +323,24 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
 
 int pic_batch_free(pic_batch *b);
 
+/* pic_batch_step without a batch object, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops that must not allocate,
+ * harnesses that forbid it): the descriptor table, the batch descriptor and
+ * the work lists live in a file-scope device array of the library (about
+ * 1.2 MB, one copy per GPU, held until the process ends), staged on `stream`
+ * by small kernels at every call.  It calls no hipMalloc, hipFree, pinned
+ * host allocation or graph instantiation; the steps are launched directly.
+ * Same simulations and semantics as pic_batch_step (FP32 periodic, reduction
+ * deposit) and the same kernels, so results are bitwise those of
+ * pic_batch_step.  At most PIC_STATIC_MAX_SIMS simulations with at most
+ * PIC_STATIC_MAX_TILES tiles together, else PIC_E_ARG (nothing launched).
+ * The device holding the simulations must be current.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  Asynchronous. */
+#define PIC_STATIC_MAX_SIMS 32
+#define PIC_STATIC_MAX_TILES 16384
+int pic_batch_step_static(pic_sim *const *sims, int n, int nsteps, void *stream);
+
 /* One serving request: a simulation, the steps to run, its arrival time in
  * seconds after the start of pic_serve. */
 typedef struct {

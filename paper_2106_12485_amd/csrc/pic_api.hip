@@ -10,6 +10,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <thread>
@@ -1287,6 +1288,167 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
             }
         }
         for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(b->gexec, st));
+        return PIC_OK;
+    });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batched steps that allocate nothing: the descriptor table, the batch
+// descriptor and the work lists live in a file-scope device array instead of
+// a batch object's arena
+// ===========================================================================
+namespace {
+
+constexpr size_t align256c(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t ST_TABLE = 0;
+constexpr size_t ST_BATCH = align256c(ST_TABLE + (size_t)PIC_STATIC_MAX_SIMS * sizeof(SimDev<float>));
+constexpr size_t ST_WORK = align256c(ST_BATCH + sizeof(BatchDev));
+constexpr size_t ST_FWORK = align256c(ST_WORK + (size_t)PIC_STATIC_MAX_TILES * sizeof(int2));
+constexpr size_t ST_YWORK =
+    align256c(ST_FWORK + (size_t)PIC_STATIC_MAX_TILES * SUNITS_PER_TILE * sizeof(int2));
+constexpr size_t ST_BYTES =
+    align256c(ST_YWORK + (size_t)PIC_STATIC_MAX_TILES * SUNITS_PER_TILE * sizeof(int2));
+
+}  // namespace
+
+// One copy per GPU, held until the process ends.  Host code never uses this
+// name as an address: it takes the device address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[ST_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES];  // device address of `scratch`, per device
+
+// Device address of the current device's `scratch`, looked up once per device.
+int scratch_address(void **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PIC_E_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PIC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return PIC_OK;
+}
+
+// A descriptor written to device memory from a kernel argument.
+template <typename T>
+__global__ void k_put(T *dst, T src)
+{
+    static_assert(sizeof(T) % 4 == 0, "copied as 32-bit words");
+    const unsigned *a = reinterpret_cast<const unsigned *>(&src);
+    unsigned *b = reinterpret_cast<unsigned *>(dst);
+    for (int k = threadIdx.x; k < (int)(sizeof(T) / 4); k += blockDim.x) b[k] = a[k];
+}
+
+// The three (simulation, unit) work lists from per-simulation counts:
+// pre[l][i] is the first entry of simulation i in list l (l = 0: tiles of
+// the push, 1: units of the streaming fold, 2: of the filter + Yee).
+struct StaticLists {
+    int n;
+    int pre[3][PIC_STATIC_MAX_SIMS + 1];
+};
+
+__global__ __launch_bounds__(256) void k_lists(int2 *w0, int2 *w1, int2 *w2, StaticLists L)
+{
+    for (int l = 0; l < 3; ++l) {
+        int2 *w = l == 0 ? w0 : (l == 1 ? w1 : w2);
+        const int total = L.pre[l][L.n];
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total;
+             k += gridDim.x * blockDim.x) {
+            int i = 0;
+            while (L.pre[l][i + 1] <= k) ++i;
+            w[k] = make_int2(i, k - L.pre[l][i]);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_batch_step_static(pic_sim *const *sims, int n, int nsteps, void *stream)
+{
+    return guarded<int>([&]() -> int {
+        if (n < 0 || nsteps < 0 || (n > 0 && !sims)) return fail(PIC_E_ARG, "bad batch call");
+        if (n == 0 || nsteps == 0) return PIC_OK;
+        if (n > PIC_STATIC_MAX_SIMS)
+            return fail(PIC_E_ARG, "pic_batch_step_static holds at most PIC_STATIC_MAX_SIMS (" +
+                                       std::to_string(PIC_STATIC_MAX_SIMS) + ") simulations");
+        StaticLists lists{};
+        lists.n = n;
+        int rf = -1;
+        for (int i = 0; i < n; ++i) {
+            const pic_sim *s = sims[i];
+            if (!s || s->cfg.fp64 || s->cfg.moving_window || s->cfg.deposit_mode != 0)
+                return fail(PIC_E_ARG, "batches hold FP32 periodic simulations with the "
+                                       "reduction deposit only");
+            const pic_cfg &c = s->cfg;
+            const int r = c.filter_passes > 0 ? c.filter_passes + (c.filter_compensate ? 1 : 0) : 0;
+            rf = i == 0 ? r : (r == rf ? rf : -1);
+        }
+        long long tot[3] = {0, 0, 0};
+        for (int i = 0; i < n; ++i) {
+            const Layout &L = sims[i]->L;
+            const long long cnt[3] = {L.ntiles, rf >= 0 ? fold_units(L.ntx, L.nty) : 0,
+                                      rf >= 0 ? yee_units(L.nxs, sims[i]->cfg.ny, rf) : 0};
+            for (int l = 0; l < 3; ++l) {
+                lists.pre[l][i] = (int)tot[l];
+                tot[l] += cnt[l];
+            }
+        }
+        if (tot[0] > PIC_STATIC_MAX_TILES || tot[1] > PIC_STATIC_MAX_TILES * SUNITS_PER_TILE ||
+            tot[2] > PIC_STATIC_MAX_TILES * SUNITS_PER_TILE)
+            return fail(PIC_E_ARG, "pic_batch_step_static holds at most PIC_STATIC_MAX_TILES (" +
+                                       std::to_string(PIC_STATIC_MAX_TILES) +
+                                       ") tiles over all simulations");
+        for (int l = 0; l < 3; ++l) lists.pre[l][n] = (int)tot[l];
+        void *base = nullptr;
+        int rc = scratch_address(&base);
+        if (rc) return rc;
+        char *sc = static_cast<char *>(base);
+        SimDev<float> *table = reinterpret_cast<SimDev<float> *>(sc + ST_TABLE);
+        BatchDev *bd = reinterpret_cast<BatchDev *>(sc + ST_BATCH);
+        int2 *work = reinterpret_cast<int2 *>(sc + ST_WORK);
+        int2 *fwork = reinterpret_cast<int2 *>(sc + ST_FWORK);
+        int2 *ywork = reinterpret_cast<int2 *>(sc + ST_YWORK);
+        hipStream_t st = (hipStream_t)stream;
+        // stage everything on the stream: descriptors from kernel arguments,
+        // work lists from the counts; the batch descriptor's completion count
+        // starts at zero
+        for (int i = 0; i < n; ++i) {
+            SimDev<float> dsc = sims[i]->df;
+            dsc.nsb = 1;  // batched pushes take every species of a tile at once
+            hipLaunchKernelGGL(k_put<SimDev<float>>, dim3(1), dim3(256), 0, st, table + i, dsc);
+            HIPCHK(hipGetLastError());
+        }
+        BatchDev b{};
+        b.nwork = (int)tot[0];
+        b.nsim = n;
+        b.work = work;
+        b.blocks_done = 0;
+        b.nfold = (int)tot[1];
+        b.nyee = (int)tot[2];
+        b.fold_work = fwork;
+        b.yee_work = ywork;
+        hipLaunchKernelGGL(k_put<BatchDev>, dim3(1), dim3(64), 0, st, bd, b);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_lists, dim3(64), dim3(256), 0, st, work, fwork, ywork, lists);
+        HIPCHK(hipGetLastError());
+        for (int k = 0; k < nsteps; ++k)
+            HIPCHK(launch_batch_step<float>(table, bd, (int)tot[0], st, rf, (int)tot[1],
+                                            (int)tot[2]));
         return PIC_OK;
     });
 }

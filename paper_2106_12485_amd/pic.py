@@ -131,6 +131,8 @@ def lib():
         L.pic_batch_step.argtypes = [_P, C.POINTER(_P), _I, _I, _P]
         L.pic_batch_free.restype = _I
         L.pic_batch_free.argtypes = [_P]
+        L.pic_batch_step_static.restype = _I
+        L.pic_batch_step_static.argtypes = [C.POINTER(_P), _I, _I, _P]
         L.pic_serve.restype = _I
         L.pic_serve.argtypes = [C.POINTER(Request), _I, _P, C.c_size_t, C.POINTER(ServeOpts),
                                 C.POINTER(Result), _DP, _LL, _LLP, _P]
@@ -370,6 +372,15 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_step_static(sims, nsteps=1, stream=None):
+    """pic_batch_step_static: step `sims` together with no batch object (the
+    library's own device array holds the descriptors; nothing is allocated)."""
+    import torch
+    arr = (_P * len(sims))(*[s._h for s in sims])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().pic_batch_step_static(arr, len(sims), int(nsteps), _P(st.cuda_stream)))
 
 
 def serve(requests, budget_bytes, batched=True, chunk_steps=10, max_batch=0, device="cuda",
