@@ -79,6 +79,12 @@ def parse():
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-coverage", action="store_true",
+                    help="only time the oracle over the measurement plan's coverage (the "
+                         "64x64 and 2000x256 runs in full, 20 steps of the two clouds, 64 "
+                         "steps of the 8000x512 run in the parallel-for mode) and print it")
+    ap.add_argument("--phase-step", type=int, default=500,
+                    help="first step of the second timed window (0 = skip it)")
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up and timed steps only (for rocprofv3)")
     ap.add_argument("--direct", action="store_true",
@@ -93,6 +99,29 @@ def parse():
                     help="only run a plain device copy of MIB MiB five times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_peak_gbs(mib=1024, reps=5):
+    """Measured device-copy bandwidth (read + write bytes per second), the
+    practical ceiling of a streaming kernel on this GPU, best of reps."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
 
 
 def copy_calibration(mib):
@@ -157,9 +186,8 @@ def serving_leg(nreq, budget_gb, chunk=10):
     return out
 
 
-def cpu_baseline(w, nsteps):
-    """Time the FP64 oracle (single-threaded C) on the same workload: its own
-    load, then nsteps full steps."""
+def oracle_for(w):
+    """The FP64 oracle loaded with workload w (its own loader and laser)."""
     from oracle import OracleSim, Species
     o = OracleSim(w.nx, w.ny, w.lx, w.ly, w.dt, window=w.moving_window,
                   filter_passes=w.filter_passes, filter_compensate=w.filter_compensate,
@@ -169,6 +197,43 @@ def cpu_baseline(w, nsteps):
     if w.laser is not None:
         L = w.laser
         o.add_laser(L.a0, L.omega0, L.W0, L.fwhm, L.x_center, L.focus, L.axis, L.pol)
+    return o
+
+
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+
+
+def cpu_coverage():
+    """The oracle over the measurement plan's CPU coverage: particle pushes per
+    second (particles at each step summed over the steps, / wall time)."""
+    from inputs import WORKLOADS
+    plan = (("thermal_64x64", None, 1), ("lwfa_2000x256", None, 1),
+            ("clouds_1024x1024", 20, 1), ("clouds_1024x1024", 20, host_threads()),
+            ("lwfa_8000x512", 64, host_threads()))
+    rows = []
+    for name, nsteps, threads in plan:
+        w = WORKLOADS[name]()
+        o = oracle_for(w)
+        o.set_threads(threads)
+        k = nsteps or w.steps
+        pushes = 0.0
+        t0 = time.perf_counter()
+        for _ in range(k):
+            pushes += sum(o.count(j) for j in range(len(w.species)))
+            o.step(1)
+        dt = time.perf_counter() - t0
+        rows.append(dict(workload=name, steps=k, threads=threads, seconds=round(dt, 2),
+                         pushes=int(pushes), pushes_per_s=pushes / dt))
+        print(json.dumps(rows[-1]), flush=True)
+        del o
+    return rows
+
+
+def cpu_baseline(w, nsteps):
+    """Time the FP64 oracle (single-threaded C) on the same workload: its own
+    load, then nsteps full steps."""
+    o = oracle_for(w)
     n = sum(o.count(k) for k in range(len(w.species)))
     t0 = time.perf_counter()
     o.step(nsteps)
@@ -178,7 +243,7 @@ def cpu_baseline(w, nsteps):
                       "one thread" % (nsteps, w.name, n),
                seconds=round(dt, 3))
     # the same oracle with the paper's parallel-for particle loop on the host cores
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    threads = host_threads()
     o.set_threads(threads)
     t0 = time.perf_counter()
     o.step(nsteps)
@@ -208,6 +273,9 @@ def main():
     if args.serve_only:
         print(json.dumps(serving_leg(args.serve_requests, args.budget_gb)))
         return
+    if args.cpu_coverage:
+        print(json.dumps(dict(cpu_coverage=cpu_coverage(), cores=host_threads())))
+        return
     w = WORKLOADS[args.workload]()
     sim = Simulation(w, fp64=args.fp64, deposit=args.deposit)
     nparts = sum(sim.count(k) for k in range(len(w.species)))
@@ -230,18 +298,22 @@ def main():
     elapsed = t1 - t0
     ms_per_step = elapsed * 1e3 / args.steps
     value = nparts * args.steps / elapsed
-
-    # per-kernel split over the same number of steps, HIP events recorded on
-    # the stream the kernels run on
-    sim.timing(True)
-    sim.step(args.steps)
-    tk = sim.timing_read()
-    sim.timing(False)
-    ms_push, n_push = tk["push_deposit"]
-    avg_push_s = ms_push / max(n_push, 1) * 1e-3
     ncell = w.nx * w.ny
-    alg_bytes = nparts * BYTES_PER_PARTICLE[args.fp64] + ncell * BYTES_PER_CELL[args.fp64]
-    achieved = alg_bytes / avg_push_s / 1e9
+
+    def kernel_pass(nsteps):
+        """Per-kernel split over nsteps direct launches, HIP events recorded
+        on the stream the kernels run on; the push's roofline over them."""
+        sim.timing(True)
+        sim.step(nsteps)
+        tk_ = sim.timing_read()
+        sim.timing(False)
+        ms_push, n_push = tk_["push_deposit"]
+        avg_s = ms_push / max(n_push, 1) * 1e-3
+        npart = sum(sim.count(k) for k in range(len(w.species)))
+        alg = npart * BYTES_PER_PARTICLE[args.fp64] + ncell * BYTES_PER_CELL[args.fp64]
+        return tk_, avg_s, alg, alg / avg_s / 1e9
+
+    tk, avg_push_s, alg_bytes, achieved = kernel_pass(args.steps)
 
     # per-step latency distribution (events around each replayed step)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -273,9 +345,39 @@ def main():
                              p99=round(float(np.percentile(lat, 99)), 4)),
         particles_end=int(n_end), status=int(status),
     )
+    # a second window later in the run: for the two clouds, steps 500-600,
+    # when the clouds have crossed and the tiles' loads are no longer uniform
+    done = args.warmup + 3 * args.steps
+    if args.phase_step > 0 and args.phase_step >= done and w.steps >= args.phase_step + 100:
+        sim.step(args.phase_step - done)
+        tp, avg_p, alg_p, ach_p = kernel_pass(100)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(100)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_p = e0.elapsed_time(e1) / 100
+        nph = sum(sim.count(k) for k in range(len(w.species)))
+        line["phase"] = dict(
+            steps="%d-%d" % (args.phase_step + 100, args.phase_step + 200),
+            kernel_steps="%d-%d" % (args.phase_step, args.phase_step + 100),
+            ms_per_step=round(ms_p, 4), pushes_per_s=nph / (ms_p * 1e-3),
+            roofline=dict(bound="hbm", achieved=round(ach_p, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(ach_p / HBM_PEAK_GBS, 4), traffic=None,
+                          kernel="k_push_deposit", avg_launch_ms=round(avg_p * 1e3, 4),
+                          alg_bytes_per_launch=int(alg_p)),
+            kernel_ms_per_step={k: round(v[0] / max(v[1], 1), 4) for k, v in tp.items() if v[1]},
+            status=int(sim.status()))
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    cp = copy_peak_gbs()
+    line["roofline"]["copy_peak"] = round(cp, 1)
+    line["roofline"]["frac_of_copy_peak"] = round(achieved / cp, 4)
+    if "phase" in line:
+        line["phase"]["roofline"]["frac_of_copy_peak"] = round(line["phase"]["roofline"]["achieved"] / cp, 4)
     if args.serve_requests > 0:
         sv = serving_leg(args.serve_requests, args.budget_gb)
         line["serving"] = sv

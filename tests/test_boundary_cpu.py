@@ -180,7 +180,12 @@ def test_product_code_does_not_reach_the_oracle():
     tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
     users = [f.name for f in tree.body if isinstance(f, ast.FunctionDef)
              and "oracle" in set(imports(f))]
-    assert users == ["cpu_baseline"], users
+    assert users == ["oracle_for"], users
+    # ... and only the CPU-baseline legs call that loader
+    callers = sorted(f.name for f in tree.body if isinstance(f, ast.FunctionDef)
+                     and any(isinstance(n, ast.Call) and getattr(n.func, "id", "") == "oracle_for"
+                             for n in ast.walk(f)))
+    assert callers == ["cpu_baseline", "cpu_coverage"], callers
     assert "oracle" not in {m for n in tree.body if not isinstance(n, ast.FunctionDef)
                             for m in imports(n)}
 
