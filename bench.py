@@ -89,7 +89,7 @@ def parse():
                     help="warm-up and timed steps only (for rocprofv3)")
     ap.add_argument("--direct", action="store_true",
                     help="with --profile-only: launch kernels directly, not from the graph")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving leg (0 = skip it)")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg and print its JSON")
@@ -135,12 +135,14 @@ def copy_calibration(mib):
     print(json.dumps(dict(copy_bytes=n * 4, launches=5)))
 
 
-def serving_leg(nreq, budget_gb, chunk=10):
+def serving_leg(nreq, budget_gb, chunk=10, rate_ratio=4):
     """Stream of independent periodic plasmas (grids 64^2..512^2, 4/16/64 ppc,
-    thermal or two-stream, 200 steps each) served within an HBM budget:
-    capacity with every request present at t = 0, one at a time vs continuous
-    batching; then latency with Poisson arrivals at the one-at-a-time service
-    rate."""
+    thermal or two-stream, 200 steps each) served within an HBM budget: every
+    request present at t = 0, then Poisson arrivals at 0.5, 1 and 2 times the
+    one-at-a-time service rate; each load served one at a time, in lockstep
+    batches and in multi-rate batches (cheaper requests take up to rate_ratio
+    times as many steps per chunk).  Request latency p50/p99 and throughput
+    for every mode at every load."""
     from inputs import serving_requests
     from paper_2106_12485_amd import serve
     budget = int(budget_gb * 2 ** 30)
@@ -161,28 +163,31 @@ def serving_leg(nreq, budget_gb, chunk=10):
                     pushes_per_s=pushes(res) / span,
                     request_latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 3),
                                             p99=round(float(np.percentile(lat, 99)), 3)),
-                    step_ms=dict(p50=round(float(np.percentile(sm, 50)), 4),
-                                 p99=round(float(np.percentile(sm, 99)), 4), n=int(len(sm))))
+                    chunk_step_ms=dict(p50=round(float(np.percentile(sm, 50)), 4),
+                                       p99=round(float(np.percentile(sm, 99)), 4),
+                                       n=int(len(sm))))
+
+    def modes(reqs):
+        return dict(
+            one_at_a_time=summary(serve(reqs, budget, batched=False, chunk_steps=chunk), reqs),
+            batched_lockstep=summary(serve(reqs, budget, batched=True, chunk_steps=chunk),
+                                     reqs),
+            batched_multirate=summary(serve(reqs, budget, batched=True, chunk_steps=chunk,
+                                            rate_ratio=rate_ratio), reqs))
+
     serve(reqs0[:4], budget, batched=True, chunk_steps=chunk)  # warm-up
-    fifo0 = summary(serve(reqs0, budget, batched=False, chunk_steps=chunk), reqs0)
-    bat0 = summary(serve(reqs0, budget, batched=True, chunk_steps=chunk), reqs0)
-    rate = fifo0["requests_per_s"]
-    rng = np.random.default_rng(0x5EED0003)
+    t0 = modes(reqs0)
+    rate = t0["one_at_a_time"]["requests_per_s"]
     out = dict(workload="serving stream: %d periodic plasmas, grids 64..512^2, ppc 4/16/64, "
                         "200 steps each, HBM budget %.0f GB" % (nreq, budget_gb),
-               chunk_steps=chunk,
-               all_at_t0=dict(one_at_a_time=fifo0, batched=bat0,
-                              speedup=round(fifo0["makespan_s"] / bat0["makespan_s"], 3)))
-    for load, key in ((1.0, "poisson_at_one_at_a_time_rate"),
-                      (2.0, "poisson_at_twice_one_at_a_time_rate")):
+               chunk_steps=chunk, rate_ratio=rate_ratio, one_at_a_time_rate_per_s=rate,
+               all_at_t0=t0)
+    rng = np.random.default_rng(0x5EED0003)
+    for load in (0.5, 1.0, 2.0):
         arr = np.cumsum(rng.exponential(1.0 / (load * rate), len(reqs0)))
         arr -= arr[0]
         reqsp = [(float(a), w, n) for a, (_, w, n) in zip(arr, reqs0)]
-        out[key] = dict(rate_per_s=round(load * rate, 3),
-                        one_at_a_time=summary(serve(reqsp, budget, batched=False,
-                                                    chunk_steps=chunk), reqsp),
-                        batched=summary(serve(reqsp, budget, batched=True, chunk_steps=chunk),
-                                        reqsp))
+        out["poisson_%gx" % load] = dict(rate_per_s=round(load * rate, 3), **modes(reqsp))
     return out
 
 
@@ -381,10 +386,14 @@ def main():
     if args.serve_requests > 0:
         sv = serving_leg(args.serve_requests, args.budget_gb)
         line["serving"] = sv
-        bp = sv["poisson_at_one_at_a_time_rate"]["batched"]
-        line["latency_ms"] = dict(p50=bp["step_ms"]["p50"], p99=bp["step_ms"]["p99"],
-                                  what="one batched step of the serving loop, Poisson "
-                                       "arrivals at the one-at-a-time service rate")
+        p1 = sv["poisson_1x"]
+        line["latency_ms"] = dict(
+            p50=p1["batched_multirate"]["request_latency_ms"]["p50"],
+            p99=p1["batched_multirate"]["request_latency_ms"]["p99"],
+            what="request latency (completion - arrival) of the serving stream, Poisson "
+                 "arrivals at the one-at-a-time service rate, multi-rate continuous batching",
+            one_at_a_time=p1["one_at_a_time"]["request_latency_ms"],
+            batched_lockstep=p1["batched_lockstep"]["request_latency_ms"])
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line))

@@ -63,7 +63,8 @@ enum {
     PIC_E_NOMEM = -3,    /* arena smaller than pic_mem_bytes() */
     PIC_E_CAPACITY = -4, /* a tile or outbox ran out of particle slots */
     PIC_E_HIP = -5,      /* a HIP runtime call failed */
-    PIC_E_STATE = -6     /* call not valid in the handle's current state */
+    PIC_E_STATE = -6,    /* call not valid in the handle's current state */
+    PIC_E_CANCELLED = -7 /* a serving request was cancelled before it finished */
 };
 
 typedef struct pic_sim pic_sim;
@@ -342,39 +343,53 @@ int pic_batch_free(pic_batch *b);
 int pic_batch_step_static(pic_sim *const *sims, int n, int nsteps, void *stream);
 
 /* One serving request: a simulation, the steps to run, its arrival time in
- * seconds after the start of pic_serve. */
+ * seconds after the start of pic_serve, and a deadline at which it is
+ * cancelled if not finished (cancel_s <= 0: never). */
 typedef struct {
     pic_cfg cfg;
     int nsteps;
     double arrival_s;
+    double cancel_s;
 } pic_request;
 
 typedef struct {
-    double admit_s;      /* when it got memory and was initialised */
-    double done_s;       /* when its last step finished */
-    pic_diag diag;       /* diagnostics after the last step */
-    int status;          /* PIC_OK or the error that ended it */
+    double admit_s;      /* when it got memory and was initialised (0: never) */
+    double done_s;       /* when its last step finished, or when it was cancelled */
+    pic_diag diag;       /* diagnostics after the last step done */
+    int status;          /* PIC_OK, PIC_E_CANCELLED or the error that ended it */
 } pic_result;
 
 typedef struct {
     int batched;         /* 1: continuous batching; 0: one at a time, in order */
     int chunk_steps;     /* steps between admission points (>= 1) */
     int max_batch;       /* most simulations running at once (<= 0: 256) */
-    int diag_every;      /* unused if 0; else pic_energy each that many steps */
+    int rate_ratio;      /* batched: a request that costs c times less than the
+                            largest one running takes min(c, rate_ratio) times as
+                            many steps per chunk (<= 1: every request in lockstep) */
+    const volatile int *cancel; /* NULL, or n flags the caller may set from another
+                            thread while pic_serve runs: cancel[i] != 0 cancels
+                            request i at the next chunk boundary */
 } pic_serve_opts;
 
-/* Serve n requests in real time: a request is queued at its arrival time,
- * admitted (first fit, in arrival order) when its pic_mem_bytes fits in the
- * free part of `arena` (the HBM budget), initialised on a stream of its own
- * while the running set keeps stepping, stepped with the running set in
- * lockstep chunks of at most chunk_steps (shared launches, pic_batch_step; a
- * set of one runs its own step graph), and retired when done, freeing its
- * memory.  Batched serving takes FP32 periodic requests with the reduction
- * deposit; others end with PIC_E_ARG.  One at a time (batched = 0) runs the
- * requests alone, in arrival order.  out[i] receives request i's times and final diagnostics.  step_ms
- * (capacity cap_steps, may be NULL) receives the time per step of every chunk
- * and *n_steps their number.  The call returns when all its device work is
- * done.  Returns PIC_OK or the first host-side error. */
+/* Serve n requests in real time (the work is the paper's cycle of Sec. 2.2 on
+ * many independent simulations; no paper passage defines the loop itself): a
+ * request is queued at its arrival time, admitted (first fit, in arrival
+ * order) when its pic_mem_bytes fits in the free part of `arena` (the HBM
+ * budget), initialised on a stream of its own while the running set keeps
+ * stepping, stepped with the running set in chunks of at most chunk_steps
+ * (shared launches, pic_batch_step; a set of one runs its own step graph;
+ * with rate_ratio > 1, cheaper requests take extra steps per chunk in shared
+ * launches of their own, pic_batch_step_static), and retired when done,
+ * freeing its memory.  A request cancelled (cancel_s passed, or its cancel
+ * flag set) is retired at the next chunk boundary with PIC_E_CANCELLED and the
+ * diagnostics of the steps it did, freeing its memory for the queue; a
+ * queued one is dropped.  Batched serving takes FP32 periodic requests with
+ * the reduction deposit; others end with PIC_E_ARG.  One at a time
+ * (batched = 0) runs the requests alone, in arrival order.  out[i] receives
+ * request i's times and final diagnostics.  step_ms (capacity cap_steps, may
+ * be NULL) receives the time per step of every chunk and *n_steps their
+ * number.  The call returns when all its device work is done.  Returns
+ * PIC_OK or the first host-side error. */
 int pic_serve(const pic_request *reqs, int n, void *arena, size_t arena_bytes,
               const pic_serve_opts *opts, pic_result *out, double *step_ms,
               long long cap_steps, long long *n_steps, void *stream);

@@ -8,4 +8,4 @@ from .pic import (Simulation, Batch, batch_step_static, serve, PicError, make_cf
                   lib,
                   KERNEL_NAMES,
                   PIC_OK, PIC_E_ARG, PIC_E_CFL, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP,
-                  PIC_E_STATE)
+                  PIC_E_STATE, PIC_E_CANCELLED)

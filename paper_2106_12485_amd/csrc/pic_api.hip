@@ -1074,6 +1074,7 @@ const char *pic_strerror(int code)
     case PIC_E_CAPACITY: return "particle capacity exceeded";
     case PIC_E_HIP: return "HIP runtime error";
     case PIC_E_STATE: return "invalid state";
+    case PIC_E_CANCELLED: return "cancelled";
     default: return "unknown error";
     }
 }
@@ -1504,6 +1505,7 @@ struct Active {
     pic_sim *sim;
     size_t off, bytes;
     int left;
+    double cost;  // relative work of one step (its arena size)
 };
 
 }  // namespace
@@ -1600,7 +1602,43 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
                     continue;
                 }
                 out[r].admit_s = now();
-                active.push_back(Active{r, sim, (size_t)off, need, std::max(0, reqs[r].nsteps)});
+                active.push_back(Active{r, sim, (size_t)off, need, std::max(0, reqs[r].nsteps),
+                                        (double)need});
+            }
+        };
+        auto cancelled = [&](int r, double tnow) {
+            return (reqs[r].cancel_s > 0 && tnow >= reqs[r].cancel_s) ||
+                   (opts->cancel && opts->cancel[r] != 0);
+        };
+        // cancellation: queued requests are dropped, running ones retired with
+        // the diagnostics of the steps they did (the step stream is idle here:
+        // every chunk is waited for before the loop comes round)
+        auto cancel = [&] {
+            const double tnow = now();
+            for (size_t qi = 0; qi < queue.size();) {
+                const int r = queue[qi];
+                if (!cancelled(r, tnow)) {
+                    ++qi;
+                    continue;
+                }
+                out[r].status = PIC_E_CANCELLED;
+                out[r].done_s = tnow;
+                ++done;
+                queue.erase(queue.begin() + qi);
+            }
+            for (size_t ai = 0; ai < active.size();) {
+                Active &a = active[ai];
+                if (a.left <= 0 || !cancelled(a.req, tnow)) {
+                    ++ai;
+                    continue;
+                }
+                (void)pic_energy(a.sim, &out[a.req].diag, sa);
+                out[a.req].status = PIC_E_CANCELLED;
+                out[a.req].done_s = now();
+                pic_free(a.sim);
+                alloc.give(a.off, a.bytes);
+                ++done;
+                active.erase(active.begin() + ai);
             }
         };
         auto retire = [&] {
@@ -1620,6 +1658,7 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
         };
         while (done < n && rc == PIC_OK) {
             admit();
+            cancel();
             retire();
             if (active.empty()) {
                 if (queue.empty() && next < n) {
@@ -1639,16 +1678,50 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
             // a batch of one runs the simulation's own step graph
             rc = sims.size() > 1 ? pic_batch_step(batch, sims.data(), (int)sims.size(), k, sa)
                                  : pic_step(sims[0], k, sa);
-            (void)hipEventRecord(e1, sa);
             if (rc) break;
+            // multi-rate: a request costing c times less than the largest one
+            // takes min(c, rate_ratio) chunks' worth of steps, the extra ones
+            // in shared launches of the cheaper requests only, k steps each
+            std::vector<int> extra(active.size(), 0);
+            if (opts->batched && opts->rate_ratio > 1 && active.size() > 1) {
+                double cmax = 0;
+                for (const Active &a : active) cmax = std::max(cmax, a.cost);
+                int rounds = 0;
+                for (size_t ai = 0; ai < active.size(); ++ai) {
+                    const Active &a = active[ai];
+                    const int rate = (int)std::min<double>(opts->rate_ratio, cmax / a.cost);
+                    extra[ai] = std::max(0, std::min(rate - 1, (a.left - k) / k));
+                    rounds = std::max(rounds, extra[ai]);
+                }
+                std::vector<pic_sim *> sub;
+                for (int u = 1; u <= rounds && rc == PIC_OK; ++u) {
+                    sub.clear();
+                    long long tiles = 0;
+                    for (size_t ai = 0; ai < active.size(); ++ai)
+                        if (extra[ai] >= u && (int)sub.size() < PIC_STATIC_MAX_SIMS &&
+                            tiles + active[ai].sim->L.ntiles <= PIC_STATIC_MAX_TILES) {
+                            sub.push_back(active[ai].sim);
+                            tiles += active[ai].sim->L.ntiles;
+                        } else if (extra[ai] >= u) {
+                            extra[ai] = u - 1;  // no room this round: fewer extra steps
+                        }
+                    if (!sub.empty())
+                        rc = pic_batch_step_static(sub.data(), (int)sub.size(), k, sa);
+                }
+                if (rc) break;
+            }
+            (void)hipEventRecord(e1, sa);
             admit();  // while the chunk runs
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             if (step_ms && ns < cap_steps) step_ms[ns] = ms / k;
             ++ns;
-            for (Active &a : active)
-                if (std::find(sims.begin(), sims.end(), a.sim) != sims.end()) a.left -= k;
+            for (size_t ai = 0; ai < active.size(); ++ai) {
+                Active &a = active[ai];
+                if (std::find(sims.begin(), sims.end(), a.sim) != sims.end())
+                    a.left -= k * (1 + (ai < extra.size() ? extra[ai] : 0));
+            }
         }
         for (Active &a : active) pic_free(a.sim);
         if (n_steps) *n_steps = ns;

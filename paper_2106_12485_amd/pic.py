@@ -20,6 +20,7 @@ KERNEL_NAMES = ("push_deposit", "settle", "fold", "filter", "yee", "window", "or
 
 PIC_OK, PIC_E_ARG, PIC_E_CFL, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
+PIC_E_CANCELLED = -7
 
 
 class SpeciesCfg(C.Structure):
@@ -53,7 +54,8 @@ class Diag(C.Structure):
 
 
 class Request(C.Structure):
-    _fields_ = [("cfg", Cfg), ("nsteps", C.c_int), ("arrival_s", C.c_double)]
+    _fields_ = [("cfg", Cfg), ("nsteps", C.c_int), ("arrival_s", C.c_double),
+                ("cancel_s", C.c_double)]
 
 
 class Result(C.Structure):
@@ -63,7 +65,7 @@ class Result(C.Structure):
 
 class ServeOpts(C.Structure):
     _fields_ = [("batched", C.c_int), ("chunk_steps", C.c_int), ("max_batch", C.c_int),
-                ("diag_every", C.c_int)]
+                ("rate_ratio", C.c_int), ("cancel", C.POINTER(C.c_int))]
 
 
 class PicError(RuntimeError):
@@ -384,19 +386,29 @@ def batch_step_static(sims, nsteps=1, stream=None):
 
 
 def serve(requests, budget_bytes, batched=True, chunk_steps=10, max_batch=0, device="cuda",
-          max_step_records=1 << 16):
-    """Serve `requests` = [(arrival_s, workload, nsteps), ...] through the
-    native continuous-batching loop within an HBM budget of budget_bytes.
-    Returns per-request times / diagnostics and the per-step batch times."""
+          max_step_records=1 << 16, rate_ratio=1, cancel_flags=None):
+    """Serve `requests` = [(arrival_s, workload, nsteps[, cancel_s]), ...]
+    through the native continuous-batching loop within an HBM budget of
+    budget_bytes.  cancel_flags: None, or an int32 numpy array of one flag per
+    request that another thread may set while this call runs (nonzero cancels
+    the request).  Returns per-request times / diagnostics and the per-step
+    batch times."""
     import torch
     n = len(requests)
     reqs = (Request * n)()
-    for i, (arr, w, nsteps) in enumerate(requests):
+    for i, rq in enumerate(requests):
+        arr, w, nsteps = rq[:3]
         reqs[i].cfg = make_cfg(w)
         reqs[i].nsteps = int(nsteps)
         reqs[i].arrival_s = float(arr)
+        reqs[i].cancel_s = float(rq[3]) if len(rq) > 3 and rq[3] is not None else 0.0
     out = (Result * n)()
-    opts = ServeOpts(int(bool(batched)), int(chunk_steps), int(max_batch), 0)
+    flags = None
+    if cancel_flags is not None:
+        assert cancel_flags.dtype == np.int32 and cancel_flags.size >= n
+        assert cancel_flags.flags["C_CONTIGUOUS"]
+        flags = cancel_flags.ctypes.data_as(C.POINTER(C.c_int))
+    opts = ServeOpts(int(bool(batched)), int(chunk_steps), int(max_batch), int(rate_ratio), flags)
     arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
     step_ms = np.zeros(max_step_records)
     nsteps_out = C.c_longlong(0)
@@ -404,7 +416,8 @@ def serve(requests, budget_bytes, batched=True, chunk_steps=10, max_batch=0, dev
     _check(lib().pic_serve(reqs, n, _P(arena.data_ptr()), arena.numel(), C.byref(opts), out,
                            _dp(step_ms), len(step_ms), C.byref(nsteps_out), _P(st.cuda_stream)))
     res = []
-    for i, (arr, w, nsteps) in enumerate(requests):
+    for i, rq in enumerate(requests):
+        arr, w = rq[0], rq[1]
         r = out[i]
         res.append(dict(arrival_s=float(arr), admit_s=r.admit_s, done_s=r.done_s,
                         latency_s=r.done_s - float(arr), status=r.status,

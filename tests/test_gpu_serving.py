@@ -171,3 +171,83 @@ def test_batched_members_match_the_oracle(halos):
         compare_state(s, om, w, False, "batched " + w.name)
         om.close()
     b.close()
+
+
+def _serve_workspace_bytes(ws):
+    """Bytes pic_serve takes from the front of its arena for the batch
+    workspace (up to 256 running simulations, every request's tiles)."""
+    from paper_2106_12485_amd import lib
+    tiles = sum(((w.nx + 15) // 16) * ((w.ny + 15) // 16) for w in ws)
+    return (lib().pic_batch_mem_bytes(256, tiles) + 255) // 256 * 256
+
+
+def test_serving_cancellation_frees_memory_for_the_queue():
+    """A long request cancelled by its deadline is retired with
+    PIC_E_CANCELLED and the diagnostics of the steps it did; the request
+    that did not fit beside it is admitted only after its memory was given
+    back, and ends exactly as it does alone."""
+    from paper_2106_12485_amd import PIC_E_CANCELLED
+    a = Workload("long_256x256", 256, 256, 25.6, 25.6, 0.07, 0,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.1,) * 3)], seed=31)
+    b = Workload("short_128x128", 128, 128, 12.8, 12.8, 0.07, 0,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.1,) * 3)], seed=32)
+    c = Workload("queued_256x256", 256, 256, 25.6, 25.6, 0.07, 0,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.2,) * 3)], seed=33)
+    ws = [a, b, c]
+    assert mem_bytes(c) <= mem_bytes(a)
+    budget = _serve_workspace_bytes(ws) + mem_bytes(a) + mem_bytes(b) + 4096
+    reqs = [(0.0, a, 10 ** 6, 0.3), (0.0, b, 30), (0.0, c, 40)]
+    r = serve(reqs, budget, batched=True, chunk_steps=5)["results"]
+    ra, rb, rc = r
+    print("cancel:", {k: (x["status"], round(x["admit_s"], 4), round(x["done_s"], 4),
+                          x["diag"]["step"]) for k, x in zip("abc", r)}, flush=True)
+    assert ra["status"] == PIC_E_CANCELLED
+    assert 0.3 <= ra["done_s"] < 5.0
+    assert 0 < ra["diag"]["step"] < 10 ** 6
+    assert rb["status"] == 0 and rb["diag"]["step"] == 30
+    assert rc["status"] == 0 and rc["diag"]["step"] == 40
+    assert rc["admit_s"] >= ra["done_s"] - 1e-6  # waited for a's memory
+    alone = Simulation(c)
+    alone.step(40)
+    e = alone.energy()
+    assert e["e_energy"] == rc["diag"]["e_energy"] and e["b_energy"] == rc["diag"]["b_energy"]
+
+
+def test_serving_cancel_flag_from_another_thread():
+    import threading
+    import time
+    from paper_2106_12485_amd import PIC_E_CANCELLED
+    a = Workload("flagged_128x128", 128, 128, 12.8, 12.8, 0.07, 0,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.1,) * 3)], seed=34)
+    b = Workload("kept_64x64", 64, 64, 6.4, 6.4, 0.07, 0,
+                 [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.1,) * 3)], seed=35)
+    flags = np.zeros(2, dtype=np.int32)
+    th = threading.Timer(0.2, lambda: flags.__setitem__(0, 1))
+    th.start()
+    t0 = time.time()
+    r = serve([(0.0, a, 10 ** 6), (0.0, b, 20)], 1 << 30, batched=True, chunk_steps=5,
+              cancel_flags=flags)["results"]
+    th.join()
+    assert time.time() - t0 < 30
+    # the flag is set 0.2 s after the timer starts, a little before the serving
+    # loop's own clock does
+    assert r[0]["status"] == PIC_E_CANCELLED and r[0]["done_s"] >= 0.15
+    assert r[1]["status"] == 0 and r[1]["diag"]["step"] == 20
+
+
+def test_multirate_chunks_give_the_same_results():
+    """With rate_ratio > 1 cheap requests take extra steps per chunk in
+    launches of their own; every request still ends bitwise as in lockstep
+    serving."""
+    reqs = [(0.0, w, 60) for _, w in serving_requests(n_requests=8, grids=(64, 128, 256),
+                                                       ppcs=((2, 2), (4, 4)), steps=60)]
+    lock = serve(reqs, 8 << 30, batched=True, chunk_steps=5, rate_ratio=1)["results"]
+    multi = serve(reqs, 8 << 30, batched=True, chunk_steps=5, rate_ratio=8)["results"]
+    for (t, w, n), a, b in zip(reqs, lock, multi):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["diag"]["step"] == b["diag"]["step"] == n
+        assert a["diag"]["e_energy"] == b["diag"]["e_energy"]
+        assert a["diag"]["b_energy"] == b["diag"]["b_energy"]
+        assert np.array_equal(a["diag"]["n_particles"], b["diag"]["n_particles"])
+    print("multirate done_s lockstep", [round(x["done_s"], 4) for x in lock],
+          "multirate", [round(x["done_s"], 4) for x in multi], flush=True)
