@@ -113,8 +113,11 @@ typedef struct {
     int fp64;            /* 0: FP32 particles/fields/current, 1: FP64 */
     unsigned long long seed;
     int load;            /* 1: load every species at init, 0: start empty */
-    double capacity_factor; /* particle slots per tile = factor * ppc * 256
-                               (0 selects 3.0) */
+    double capacity_factor; /* particle slots per buffer and species = factor *
+                               the species' largest count (its initial load on
+                               a periodic box; the whole box at its ppc with the
+                               moving window or without a load), shared among
+                               the tiles by count (0 selects 2.0) */
     int deposit_mode;    /* how the tiles' currents are combined (the paper's
                             two strategies, Sec. 3.2):
                             0 "reduction": each tile deposits into a block of
@@ -291,7 +294,8 @@ int pic_timing_read(pic_sim *sim, double *ms, long long *launches, int nk, void 
 
 /* Geometry of the tiling: out[0] tile width, out[1] tile height, out[2]
  * tiles along x, out[3] tiles along y, out[4] storage width in x, out[5]
- * particle slots per tile of species 0, out[6] outbox slots per tile. */
+ * particle slots per buffer of species 0 (shared among the tiles), out[6]
+ * outbox slots per tile. */
 int pic_layout(const pic_sim *sim, long long *out, int n);
 
 /* ---------------------------------------------------------------------

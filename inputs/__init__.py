@@ -136,11 +136,12 @@ def weibel512() -> Workload:
     cell per species (134,217,728 particles), u_fl,z = +-0.6, u_th = 0.1."""
     L = 51.2
     # The filaments pinch: over the 500 steps the fullest tile reaches 3.8x
-    # its initial load (and others empty), so tiles get 6x.
+    # its initial load while others empty; the particle segments follow the
+    # counts, so the default pool of twice the load suffices.
     return Workload("weibel_512x512", 512, 512, L, L, 0.07, 500,
                     [SpeciesSpec(-1.0, 1.0, ppc=(16, 16), uth=(0.1,) * 3, ufl=(0.0, 0.0, 0.6)),
                      SpeciesSpec(1.0, 1.0, ppc=(16, 16), uth=(0.1,) * 3, ufl=(0.0, 0.0, -0.6))],
-                    seed=SEED_BASE + 5, capacity_factor=6.0)
+                    seed=SEED_BASE + 5)
 
 
 WORKLOADS = {

@@ -69,7 +69,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Arena layout of one simulation.
 struct Layout {
     int nxs, ntx, nty, ntiles;
-    int cap[MAX_SP];
+    long long pool[MAX_SP];  // particle slots per buffer
+    int maxseg[MAX_SP];  // most slots of one tile's segment
     int cap_out;
     int push_bt, nsb;  // threads per push block; push blocks per tile
     size_t rs;  // bytes of the working precision
@@ -80,6 +81,76 @@ struct Layout {
     size_t sp_bytes[MAX_SP];
     size_t total;
 };
+
+// Particles the loader puts in each tile for species s (window origin 0, no
+// shift): per storage column, the sub-positions m whose lab-frame x, in
+// double exactly as k_load evaluates it, lies in [x_lo, x_hi), times ppc_y
+// and the tile's rows.  Empty without a load or density.
+std::vector<long long> load_counts(const pic_cfg *c, int nxs, int ntx, int nty, int s)
+{
+    std::vector<long long> cnt((size_t)ntx * nty, 0);
+    const pic_species_cfg &p = c->sp[s];
+    if (!c->load || !(p.density > 0.0)) return cnt;
+    const double dx = c->lx / c->nx;
+    std::vector<long long> col((size_t)nxs, 0);
+    for (int gx = 0; gx < c->nx; ++gx) {
+        int m_in = 0;
+        for (int m = 0; m < p.ppc_x; ++m) {
+            const double xo = ((double)m + 0.5) / (double)p.ppc_x;
+            const double xlab = ((double)gx + xo) * dx;
+            m_in += xlab >= p.x_lo && xlab < p.x_hi;
+        }
+        col[gx] = (long long)m_in * p.ppc_y;
+    }
+    for (int ty = 0; ty < nty; ++ty) {
+        const int h = std::min(TY, c->ny - ty * TY);
+        for (int tx = 0; tx < ntx; ++tx) {
+            long long n = 0;
+            for (int gx = tx * TX; gx < std::min(nxs, tx * TX + TX); ++gx) n += col[gx];
+            cnt[(size_t)tx + (size_t)ty * ntx] = n * h;
+        }
+    }
+    return cnt;
+}
+
+// Segments from per-tile counts (the host's form of the device relayout,
+// with no outflow known yet): each tile its count (+ extra, if given)
+// rounded up to 64 slots, plus a share of the rest of the pool in
+// proportion to count + average count, at most maxseg, in tile order.
+// False if the counts do not fit.
+bool layout_from_counts(const std::vector<long long> &cnt, long long pool, long long maxseg,
+                        std::vector<long long> *start, std::vector<int> *seg,
+                        const std::vector<long long> *extra = nullptr)
+{
+    const size_t n = cnt.size();
+    long long total = 0, need = 0;
+    auto want = [&](size_t t) {
+        const long long v = cnt[t] + (extra ? (*extra)[t] : 0);
+        return std::min(maxseg, (v + 63) / 64 * 64);
+    };
+    for (size_t t = 0; t < n; ++t) {
+        if (cnt[t] > maxseg) return false;
+        total += cnt[t];
+        need += want(t);
+    }
+    const long long spare = pool - need;
+    if (spare < 0) return false;
+    const double avg = n ? (double)total / (double)n : 0.0;
+    const double wsum = (double)total + avg * (double)n;
+    start->assign(n, 0);
+    seg->assign(n, 0);
+    long long at = 0;
+    for (size_t t = 0; t < n; ++t) {
+        const long long base = want(t);
+        const long long share =
+            wsum > 0 ? (long long)((double)spare * ((double)cnt[t] + avg) / wsum) / 64 * 64 : 0;
+        const long long cap = std::min(maxseg, base + share);
+        (*start)[t] = at;
+        (*seg)[t] = (int)cap;
+        at += cap;
+    }
+    return true;
+}
 
 int layout(const pic_cfg *c, Layout *L)
 {
@@ -100,7 +171,7 @@ int layout(const pic_cfg *c, Layout *L)
     const double dx = c->lx / c->nx, dy = c->ly / c->ny;
     if (!(c->dt * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy)) < 1.0))
         return fail(PIC_E_CFL, "dt violates the Courant limit dt < 1/sqrt(1/dx^2 + 1/dy^2)");
-    const double cf = c->capacity_factor > 0 ? c->capacity_factor : 3.0;
+    const double cf = c->capacity_factor > 0 ? c->capacity_factor : 2.0;
     for (int s = 0; s < c->n_species; ++s) {
         const pic_species_cfg &p = c->sp[s];
         if (p.ppc_x < 1 || p.ppc_y < 1 || p.ppc_x * p.ppc_y > 1024)
@@ -128,20 +199,37 @@ int layout(const pic_cfg *c, Layout *L)
     L->ntiles = L->ntx * L->nty;
     L->rs = c->fp64 ? 8 : 4;
     L->plane = (size_t)L->nxs * c->ny;
-    int maxcap = 64;
+    // Particle slots per buffer and species: capacity_factor times the most
+    // particles the species can hold: its initial load on a periodic box
+    // (the count is then conserved), or the whole box at its ppc with the
+    // moving window (which loads plasma as it moves) or without a load (room
+    // for particles set from the host); plus 64 slots per tile for rounding.
+    // A tile's segment holds at most 8 times a full tile at the species' ppc
+    // (this bounds the fixed-point scale of the current sums).
+    long long full_tile = 0;  // largest full-tile load over the species
     for (int s = 0; s < c->n_species; ++s) {
-        const double want = cf * c->sp[s].ppc_x * c->sp[s].ppc_y * TX * TY;
-        long long cap = ((long long)std::ceil(want) + 63) / 64 * 64;
-        cap = std::max<long long>(cap, 64);
-        if (cap > (1 << 26)) return fail(PIC_E_ARG, "capacity_factor too large");
-        L->cap[s] = (int)cap;
-        maxcap = std::max(maxcap, (int)cap);
+        const pic_species_cfg &p = c->sp[s];
+        const long long ppc = (long long)p.ppc_x * p.ppc_y;
+        long long nmax = (long long)c->nx * c->ny * ppc;
+        if (!c->moving_window && c->load && p.density > 0.0) {
+            long long n0 = 0;
+            for (long long v : load_counts(c, L->nxs, L->ntx, L->nty, s)) n0 += v;
+            nmax = n0;
+        }
+        // with the moving window, also room for the columns the next 16
+        // steps load at the right edge (a layout reserves it ahead)
+        const double inj = c->moving_window && p.density > 0.0 ? 16.0 * c->ny * ppc : 0.0;
+        const double want = cf * (double)nmax + inj + 64.0 * L->ntiles;
+        if (want > (double)(1LL << 40)) return fail(PIC_E_ARG, "capacity_factor too large");
+        L->pool[s] = ((long long)std::ceil(want) + 63) / 64 * 64;
+        L->maxseg[s] = (int)std::min<long long>(L->pool[s], 8 * ppc * TX * TY);
+        full_tile = std::max(full_tile, ppc * TX * TY);
     }
-    // outbox: a quarter of the slots per tile.  A particle crosses at most one
-    // cell per step, so only those in the tile's outer ring of cells (60 of
-    // 256) can leave: a uniformly filled tile at capacity sends at most 23% of
-    // its slots, even when every one of them moves outwards at close to c.
-    L->cap_out = std::max(64, (maxcap / 4 + 63) / 64 * 64);
+    // Outbox: a quarter of a full tile's load.  A particle crosses at most
+    // one cell per step, so only those in the tile's outer ring of cells (60
+    // of 256) can leave: a uniformly filled tile sends at most 23% of its
+    // particles, even when every one of them moves outwards at close to c.
+    L->cap_out = (int)std::max<long long>(256, (full_tile / 4 + 63) / 64 * 64);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -170,11 +258,15 @@ int layout(const pic_cfg *c, Layout *L)
     L->off_order = take((size_t)L->ntiles * L->nsb * 4);
     const size_t obs = (size_t)L->ntiles * L->cap_out;
     for (int s = 0; s < c->n_species; ++s) {
-        const size_t slots = (size_t)L->ntiles * L->cap[s];
+        const size_t slots = (size_t)L->pool[s];
         size_t b = 0;
-        // two particle buffers (packed cell + 5 components + per-tile count)
+        // two particle buffers (packed cell + 5 components + per-tile count,
+        // segment start and segment slots)
         b += 2 * (align256(slots * 4) + 5 * align256(slots * L->rs) +
-                  align256((size_t)L->ntiles * 4));
+                  2 * align256((size_t)L->ntiles * 4) + align256((size_t)L->ntiles * 8));
+        // each tile's count at the last layout check, its need there, and
+        // its last inflow
+        b += 3 * align256((size_t)L->ntiles * 4);
         // two outboxes (cell, direction byte, 5 components, per-tile count)
         b += 2 * (align256(obs * 4) + align256(obs) + 5 * align256(obs * L->rs) +
                   align256((size_t)L->ntiles * 4));
@@ -220,13 +312,14 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     // one LDS entry over its step total at most |q_p| (|v| < 1; weights and
     // path fractions <= 1).  A push block takes its tile's particles and the
     // arrivals of the last hand-off; unless it flags a capacity error, those
-    // that stay fit the tile's slots and those that leave fit the outbox, so
-    // an entry never exceeds the sum of |q_p| over slots + outbox slots of
-    // every species.  Take the largest e that keeps that bound below 2^62.
+    // that stay fit the tile's segment (at most maxseg slots) and those that
+    // leave fit the outbox, so an entry never exceeds the sum of |q_p| over
+    // maxseg + outbox slots of every species.  Take the largest e that keeps
+    // that bound below 2^62.
     double bound = 0.0;
     for (int s = 0; s < c->n_species; ++s) {
         const pic_species_cfg &p = c->sp[s];
-        bound += (double)(L.cap[s] + L.cap_out) * p.density / (p.ppc_x * p.ppc_y);
+        bound += (double)(L.maxseg[s] + L.cap_out) * p.density / (p.ppc_x * p.ppc_y);
     }
     const int e = bound > 0 ? std::min(120, 62 - (int)std::ceil(std::log2(bound))) : 60;
     d->jq = (R)std::ldexp(1.0, sizeof(R) == 4 ? e - 32 : e);
@@ -252,7 +345,7 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     for (int s = 0; s < c->n_species; ++s) {
         const pic_species_cfg &p = c->sp[s];
         SpDev<R> &P = d->sp[s];
-        const size_t slots = (size_t)L.ntiles * L.cap[s];
+        const size_t slots = (size_t)L.pool[s];
         const size_t obs = (size_t)L.ntiles * L.cap_out;
         char *q = a + L.off_sp[s];
         auto next = [&](size_t bytes) {
@@ -269,7 +362,12 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
             B.uy = (R *)next(slots * L.rs);
             B.uz = (R *)next(slots * L.rs);
             B.count = (int *)next((size_t)L.ntiles * 4);
+            P.start[b] = (long long *)next((size_t)L.ntiles * 8);
+            P.seg[b] = (int *)next((size_t)L.ntiles * 4);
         }
+        P.snap = (int *)next((size_t)L.ntiles * 4);
+        P.need = (int *)next((size_t)L.ntiles * 4);
+        P.inflow = (int *)next((size_t)L.ntiles * 4);
         for (int b = 0; b < 2; ++b) {
             P.ob_cell[b] = (int *)next(obs * 4);
             P.ob_dir[b] = (unsigned char *)next(obs);
@@ -284,7 +382,8 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
         P.qm = (R)p.q_over_m;
         P.qp = (R)qp;
         P.tau = (R)(0.5 * c->dt * p.q_over_m);
-        P.cap = L.cap[s];
+        P.pool = L.pool[s];
+        P.maxseg = L.maxseg[s];
         P.ppc_x = p.ppc_x;
         P.ppc_y = p.ppc_y;
         P.density = p.density;
@@ -313,6 +412,11 @@ double laser_eperp(const pic_laser_cfg &l, double x, double y)
 
 }  // namespace
 
+// Pushes between two work-order launches (each also checks the particle
+// layout): the first step of every 8-step graph, and before a push that
+// follows 8 others without one.
+constexpr int GRAPH_STEPS_N = 8;
+
 struct pic_sim {
     pic_cfg cfg;
     Layout L;
@@ -333,7 +437,8 @@ struct pic_sim {
     long long launches[PIC_NK];
     // diagnostics
     long long rho_prev_iter = -2;
-    long long pushes_enqueued = 0;  // directly launched pushes (work order cadence)
+    int since_order = GRAPH_STEPS_N;  // pushes enqueued since the last work order
+                                      // and layout check (at most GRAPH_STEPS)
     DevState hs;  // host copy, valid after read_state
     unsigned long long uid = 0;  // unique per pic_init (handles may reuse addresses)
 };
@@ -410,10 +515,10 @@ int enqueue_settle(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool only_if_
     return timed(s, 1, st, [&] { return Launch<R>::settle(d, st, only_if_shift, unpend); });
 }
 
-// The push's work order (heaviest tiles first) is rewritten every
-// GRAPH_STEPS steps: particle counts move slowly, and the order only has to
-// be close.
-constexpr int GRAPH_STEPS = 8;
+// The push's work order (heaviest tiles first) and the particle layout are
+// rewritten at most every GRAPH_STEPS pushes: particle counts move slowly,
+// and the order only has to be close.
+constexpr int GRAPH_STEPS = GRAPH_STEPS_N;
 
 // The push of one step, preceded by a new work order when `order` is set.
 template <typename R>
@@ -426,12 +531,14 @@ int enqueue_push(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool order)
     return timed(s, 0, st, [&] { return Launch<R>::push_deposit(d, st); });
 }
 
-// a push launched directly (not from a graph): a new order every
-// GRAPH_STEPS of them
+// a push launched directly (not from a graph): a new order after
+// GRAPH_STEPS pushes without one
 template <typename R>
 int enqueue_push_direct(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
-    return enqueue_push(s, d, st, s->pushes_enqueued++ % GRAPH_STEPS == 0);
+    const bool order = s->since_order >= GRAPH_STEPS;
+    s->since_order = order ? 1 : s->since_order + 1;
+    return enqueue_push(s, d, st, order);
 }
 
 // a1-a4: push + deposit; the leavers are then appended to their new tiles
@@ -502,6 +609,40 @@ int gauss_baseline(pic_sim *s, const SimDev<R> &d, hipStream_t st)
     return PIC_OK;
 }
 
+// With the moving window, the room per tile for the columns the next 16
+// steps load at the right edge (storage columns origin + nx .. + 15, at most
+// one per step); zero otherwise.
+std::vector<long long> window_room(const pic_cfg &c, const Layout &L, int sp, int origin)
+{
+    std::vector<long long> extra((size_t)L.ntiles, 0);
+    const pic_species_cfg &p = c.sp[sp];
+    if (!c.moving_window || !(p.density > 0.0)) return extra;
+    for (int k = 0; k < 16; ++k) {
+        const int gx = (origin + c.nx + k) % L.nxs;
+        for (int ty = 0; ty < L.nty; ++ty)
+            extra[(size_t)(gx / TX) + (size_t)ty * L.ntx] +=
+                (long long)std::min(TY, c.ny - ty * TY) * p.ppc_x * p.ppc_y;
+    }
+    return extra;
+}
+
+// Upload a species' segments to both buffers' layout arrays, and the
+// counts they were made for as the growth snapshot (synchronises: the host
+// vectors are freed on return).
+template <typename R>
+int upload_layout(const SpDev<R> &P, const std::vector<long long> &start,
+                  const std::vector<int> &seg, const std::vector<int> &snap, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(P.snap, snap.data(), snap.size() * 4, hipMemcpyHostToDevice, st));
+    for (int b = 0; b < 2; ++b) {
+        HIPCHK(hipMemcpyAsync(P.start[b], start.data(), start.size() * 8, hipMemcpyHostToDevice,
+                              st));
+        HIPCHK(hipMemcpyAsync(P.seg[b], seg.data(), seg.size() * 4, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return PIC_OK;
+}
+
 template <typename R>
 int do_init(pic_sim *s, const SimDev<R> &d, hipStream_t st)
 {
@@ -534,6 +675,17 @@ int do_init(pic_sim *s, const SimDev<R> &d, hipStream_t st)
         HIPCHK(hipMemcpyAsync(d.F[0][0], h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice,
                               st));
         HIPCHK(hipStreamSynchronize(st));
+    }
+    // segments of every tile from the load's counts, the same in both buffers
+    for (int sp = 0; sp < c.n_species; ++sp) {
+        std::vector<long long> start;
+        std::vector<int> seg;
+        const std::vector<long long> cnt = load_counts(&c, L.nxs, L.ntx, L.nty, sp);
+        const std::vector<long long> extra = window_room(c, L, sp, 0);
+        if (!layout_from_counts(cnt, L.pool[sp], L.maxseg[sp], &start, &seg, &extra))
+            return fail(PIC_E_CAPACITY, "the initial load exceeds the particle slots");
+        int rc = upload_layout(d.sp[sp], start, seg, std::vector<int>(cnt.begin(), cnt.end()), st);
+        if (rc) return rc;
     }
     if (c.load)
         for (int sp = 0; sp < c.n_species; ++sp) HIPCHK(Launch<R>::load(d, sp, st));
@@ -617,8 +769,16 @@ int do_set_particles(pic_sim *s, const SimDev<R> &d, int sp, long long n, const 
         tile[k] = gx / TX + (iy[k] / TY) * L.ntx;
         cnt[tile[k]] += 1;
     }
-    for (int t = 0; t < L.ntiles; ++t)
-        if (cnt[t] > L.cap[sp]) return fail(PIC_E_CAPACITY, "a tile exceeds its particle slots");
+    // the tiles' segments from these counts, the same in both buffers
+    std::vector<long long> sstart;
+    std::vector<int> sseg;
+    const std::vector<long long> extra = window_room(c, L, sp, origin);
+    if (!layout_from_counts(std::vector<long long>(cnt.begin(), cnt.end()), L.pool[sp],
+                            L.maxseg[sp], &sstart, &sseg, &extra))
+        return fail(PIC_E_CAPACITY, "the particles exceed the species' particle slots (or a "
+                                    "tile's largest segment)");
+    rc = upload_layout(d.sp[sp], sstart, sseg, cnt, st);
+    if (rc) return rc;
     // counting sort by tile, then one copy per array per non-empty tile
     std::vector<long long> start((size_t)L.ntiles + 1, 0);
     for (int t = 0; t < L.ntiles; ++t) start[t + 1] = start[t] + cnt[t];
@@ -639,10 +799,9 @@ int do_set_particles(pic_sim *s, const SimDev<R> &d, int sp, long long n, const 
         huz[q] = (R)uz[k];
     }
     const PartBuf<R> &P = d.sp[sp].pb[s->hs.ppar];
-    const int cap = d.sp[sp].cap;
     for (int t = 0; t < L.ntiles; ++t) {
         if (!cnt[t]) continue;
-        const size_t dst = (size_t)t * cap, src = (size_t)start[t], m = (size_t)cnt[t];
+        const size_t dst = (size_t)sstart[t], src = (size_t)start[t], m = (size_t)cnt[t];
         HIPCHK(hipMemcpyAsync(P.cell + dst, hc.data() + src, m * 4, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(P.x + dst, hx.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(P.y + dst, hy.data() + src, m * sizeof(R), hipMemcpyHostToDevice, st));
@@ -666,9 +825,11 @@ int do_get_particles(pic_sim *s, const SimDev<R> &d, int sp, long long cap, long
     rc = read_state(s, st);
     if (rc) return rc;
     const PartBuf<R> &P = d.sp[sp].pb[s->hs.ppar];
-    const int scap = d.sp[sp].cap;
     std::vector<int> cnt((size_t)L.ntiles);
+    std::vector<long long> sstart((size_t)L.ntiles);
     HIPCHK(hipMemcpyAsync(cnt.data(), P.count, cnt.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sstart.data(), d.sp[sp].start[s->hs.ppar], sstart.size() * 8,
+                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     long long n = 0;
     for (int v : cnt) n += v;
@@ -680,7 +841,7 @@ int do_get_particles(pic_sim *s, const SimDev<R> &d, int sp, long long cap, long
     long long q = 0;
     for (int t = 0; t < L.ntiles; ++t) {
         if (!cnt[t]) continue;
-        const size_t src = (size_t)t * scap, m = (size_t)cnt[t];
+        const size_t src = (size_t)sstart[t], m = (size_t)cnt[t];
         HIPCHK(hipMemcpyAsync(hc.data() + q, P.cell + src, m * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hx.data() + q, P.x + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hy.data() + q, P.y + src, m * sizeof(R), hipMemcpyDeviceToHost, st));
@@ -772,7 +933,9 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
 {
     if (s->timing) {
         for (int n = 0; n < nsteps; ++n) {
-            int rc = enqueue_step(s, d, st, s->pushes_enqueued++ % GRAPH_STEPS == 0);
+            const bool order = s->since_order >= GRAPH_STEPS;
+            s->since_order = order ? 1 : s->since_order + 1;
+            int rc = enqueue_step(s, d, st, order);
             if (rc) return rc;
         }
         return PIC_OK;
@@ -787,7 +950,16 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
         if (rc) return rc;
     }
     for (int n = 0; n < nsteps / GRAPH_STEPS; ++n) HIPCHK(hipGraphLaunch(s->gexec_n, st));
-    for (int n = 0; n < nsteps % GRAPH_STEPS; ++n) HIPCHK(hipGraphLaunch(s->gexec, st));
+    if (nsteps >= GRAPH_STEPS) s->since_order = GRAPH_STEPS;  // the last graph's order
+    for (int n = 0; n < nsteps % GRAPH_STEPS; ++n) {
+        // one-step graphs hold no work order: launch one directly when due
+        if (s->since_order >= GRAPH_STEPS) {
+            if (!d.direct) HIPCHK(Launch<R>::order(d, st));
+            s->since_order = 0;
+        }
+        HIPCHK(hipGraphLaunch(s->gexec, st));
+        ++s->since_order;
+    }
     return PIC_OK;
 }
 
@@ -901,8 +1073,17 @@ int pic_status(pic_sim *sim, void *stream)
         if (!sim) return fail(PIC_E_ARG, "sim is NULL");
         int rc = read_state(sim, (hipStream_t)stream);
         if (rc) return rc;
-        if (sim->hs.err & ERR_CAPACITY)
-            return fail(PIC_E_CAPACITY, "a tile or outbox ran out of particle slots");
+        const int e = sim->hs.err;
+        if (e & ERR_CAPACITY) {
+            std::string what;
+            const char *names[] = {"a tile's segment", "a tile's outbox", "a push block's arrival list",
+                                   "a segment while settling leavers", "the pool for a relayout",
+                                   "a segment while loading the window's new column",
+                                   "a segment during the initial load"};
+            for (int b = 0; b < 7; ++b)
+                if (e & (1 << b)) what += (what.empty() ? "" : ", ") + std::string(names[b]);
+            return fail(PIC_E_CAPACITY, "particle slots ran out: " + what);
+        }
         return PIC_OK;
     });
 }
@@ -929,7 +1110,7 @@ int pic_set_particles(pic_sim *sim, int sp, long long n, const int *ix, const in
             return fail(PIC_E_ARG, "bad sim, species or count");
         if (n > 0 && (!ix || !iy || !x || !y || !ux || !uy || !uz))
             return fail(PIC_E_ARG, "NULL particle array");
-        if (n > (long long)sim->L.ntiles * sim->L.cap[sp])
+        if (n > (long long)sim->L.pool[sp])
             return fail(PIC_E_CAPACITY, "more particles than the species has slots");
         hipStream_t st = (hipStream_t)stream;
         return DISPATCH(sim,
@@ -1058,7 +1239,8 @@ int pic_layout(const pic_sim *sim, long long *out, int n)
     return guarded<int>([&]() -> int {
         if (!sim || !out) return fail(PIC_E_ARG, "bad sim or out");
         const long long v[7] = {TX, TY, sim->L.ntx, sim->L.nty, sim->L.nxs,
-                                sim->cfg.n_species ? sim->L.cap[0] : 0, sim->L.cap_out};
+                                sim->cfg.n_species ? (long long)sim->L.pool[0] : 0LL,
+                                (long long)sim->L.cap_out};
         for (int k = 0; k < n && k < 7; ++k) out[k] = v[k];
         return PIC_OK;
     });

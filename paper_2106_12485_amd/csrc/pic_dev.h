@@ -7,8 +7,8 @@
 // plus its guard cells, so no tile's halo ever sees both window edges.
 //
 // Tiles: TX x TY cells (the paper's regions with ghost cells, Sec. 3.2).  A
-// tile owns a fixed segment of `cap` particle slots per species, of which the
-// first count[t] are live.  Fields and current are staged per tile in LDS on
+// tile owns a segment of particle slots per species and buffer (see SpDev),
+// of which the first count[t] are live.  Fields and current are staged per tile in LDS on
 // local cells [-1, TX+2) x [-1, TY+2): one guard cell below and two above,
 // which is the reach of bilinear interpolation of the staggered components
 // (one cell each way) and of the charge-conserving deposit of a particle that
@@ -45,7 +45,15 @@ __host__ __device__ constexpr int yee_units(int nxs, int ny, int rf)
 }           // largest filter halo (passes + compensator)
 constexpr int QX = TX + 2 * MAX_FR; // LDS pitch of the filter block
 constexpr int QY = TY + 2 * MAX_FR;
-constexpr int ERR_CAPACITY = 1;
+// Device error bits (DevState::err): which store ran out of slots.
+constexpr int ERR_SEG = 1;         // a tile's segment (push output)
+constexpr int ERR_OUTBOX = 2;      // a tile's outbox
+constexpr int ERR_ARRIVALS = 4;    // a push block's arrival list
+constexpr int ERR_SETTLE = 8;      // a segment while appending pending leavers
+constexpr int ERR_POOL = 16;       // the pool, for a relayout's needs
+constexpr int ERR_INJECT = 32;     // a segment while loading the window's new column
+constexpr int ERR_LOAD = 64;       // a segment during the initial load
+constexpr int ERR_CAPACITY = 127;  // any of them
 constexpr int N_RED = 16;           // result slots of the diagnostic reduction
 constexpr int NB_DIAG = 512;        // blocks of the grid-stride diagnostic kernels
 
@@ -86,15 +94,31 @@ struct PartBuf {
     int *count;       // particles per tile
 };
 
+// Particle storage of a species: two ping-pong buffers of `pool` slots in
+// which tile t owns the segment [start[b][t], start[b][t] + seg[b][t]) of
+// buffer b, its particles in the first count[t] slots.  Segments are sized
+// per tile from the particle counts (a relayout every few steps gives each
+// tile room for its count plus twice its growth since the last check, and
+// shares the rest of the pool in proportion to count + average), so a tile
+// holding several times the average load needs no uniform over-sizing.
+// The push reads its tile from buffer b and writes it to buffer b ^ 1 at the
+// latter's layout, so a new layout costs nothing beyond that push.
 template <typename R>
 struct SpDev {
-    PartBuf<R> pb[2];                 // ping-pong particle buffers: ntiles x cap
+    PartBuf<R> pb[2];                 // ping-pong particle buffers of `pool` slots
+    long long *start[2];              // per buffer: first slot of each tile's segment
+    int *seg[2];                      // per buffer: slots of each tile's segment
+    int *snap;                        // each tile's count at the last layout check
+    int *need;                        // each tile's need at the check (scratch)
+    int *inflow;                      // particles that entered each tile in its
+                                      // last step with a hand-off
     int *ob_cell[2];                  // outboxes: ntiles x cap_out
     R *ob_x[2], *ob_y[2], *ob_ux[2], *ob_uy[2], *ob_uz[2];
     unsigned char *ob_dir[2];         // dir_index of each leaver's tile step
     int *ob_count[2];                 // leavers per tile
     R qm, qp, tau;    // q/m, charge per particle, (dt/2)(q/m)
-    int cap;          // slots per tile
+    long long pool;   // slots per buffer
+    int maxseg;       // most slots one tile's segment may have
     int ppc_x, ppc_y;
     double density, x_lo, x_hi;
     double uth[3], ufl[3];
@@ -189,6 +213,18 @@ template <typename T>
 __device__ __forceinline__ gptr<T> glob(T *p)
 {
     return (gptr<T>)p;
+}
+
+// Tile t's segment of buffer b: first slot and slots.
+template <typename R>
+__device__ __forceinline__ size_t seg_start(const SpDev<R> &P, int b, int t)
+{
+    return (size_t)glob(P.start[b])[t];
+}
+template <typename R>
+__device__ __forceinline__ int seg_slots(const SpDev<R> &P, int b, int t)
+{
+    return glob(P.seg[b])[t];
 }
 
 // element at a 32-bit byte offset from a wave-uniform base pointer (keeps the

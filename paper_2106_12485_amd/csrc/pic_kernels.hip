@@ -327,7 +327,10 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
         const int n_found = sh.n_arr[s];
         const unsigned n_tot = n_own + (unsigned)min(n_found, lcap);
         const int *const list = sh.arr + (s - s0) * lcap;
-        const size_t base = (size_t)t * P.cap;
+        // the tile's segments: input at buffer ppar's layout, output at
+        // buffer ppar ^ 1's (a relayout changes only the latter)
+        const size_t base = seg_start(P, pp, t), obase_p = seg_start(P, pp ^ 1, t);
+        const int ocap = seg_slots(P, pp ^ 1, t);
         // tile-uniform base pointers, indexed with 32-bit offsets
         const int *const ic = bi.cell + base;
         const R *const ixp = bi.x + base;
@@ -335,12 +338,12 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
         const R *const iux = bi.ux + base;
         const R *const iuy = bi.uy + base;
         const R *const iuz = bi.uz + base;
-        int *const oc = bo.cell + base;
-        R *const oxp = bo.x + base;
-        R *const oyp = bo.y + base;
-        R *const oux = bo.ux + base;
-        R *const ouy = bo.uy + base;
-        R *const ouz = bo.uz + base;
+        int *const oc = bo.cell + obase_p;
+        R *const oxp = bo.x + obase_p;
+        R *const oyp = bo.y + obase_p;
+        R *const oux = bo.ux + obase_p;
+        R *const ouy = bo.uy + obase_p;
+        R *const ouz = bo.uz + obase_p;
         // deposit prefactors carry the fixed-point scale (a power of two)
         const R qjx = P.qp * d.jxs * jq, qjy = P.qp * d.jys * jq, qps = P.qp * jq;
         const R tau = P.tau;
@@ -409,7 +412,7 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
                 off = __builtin_amdgcn_readfirstlane(off);
                 if (stay) {
                     const unsigned q = (unsigned)(off + (int)__popcll(ms & below));
-                    if (q < (unsigned)P.cap) {
+                    if (q < (unsigned)ocap) {
                         const unsigned o4 = q * 4u, oR = q * (unsigned)sizeof(R);
                         at(oc, o4) = ncell;
                         at(oxp, oR) = xn;
@@ -418,7 +421,7 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
                         at(ouy, oR) = uy;
                         at(ouz, oR) = uz;
                     } else {
-                        __hip_atomic_fetch_or(&glob(d.st)->err, ERR_CAPACITY, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_or(&glob(d.st)->err, ERR_SEG, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
@@ -441,7 +444,7 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
                         glob(P.ob_uy[ob ^ 1])[o] = uy;
                         glob(P.ob_uz[ob ^ 1])[o] = uz;
                     } else {
-                        __hip_atomic_fetch_or(&glob(d.st)->err, ERR_CAPACITY, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_or(&glob(d.st)->err, ERR_OUTBOX, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
@@ -480,20 +483,27 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
             advance(p < n_tot, cell, x, y, ux, uy, uz);
         }
         if (threadIdx.x == 0 && n_found > lcap)
-            __hip_atomic_fetch_or(&glob(d.st)->err, ERR_CAPACITY, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_or(&glob(d.st)->err, ERR_ARRIVALS, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    // counts of the tile, and the counters zeroed for the block's next tile
+    // counts of the tile, the input buffer's segment set to the output's
+    // layout (so both buffers share it after a relayout; no other block reads
+    // this tile's entries), and the counters zeroed for the block's next tile
     if ((int)threadIdx.x < s1 - s0) {
         const int s = s0 + (int)threadIdx.x;
         const SpDev<R> &P = d.sp[s];
-        glob(P.pb[pp ^ 1].count)[t] = min(sh.n_out[s], P.cap);
+        const int ocap = seg_slots(P, pp ^ 1, t);
+        glob(P.pb[pp ^ 1].count)[t] = min(sh.n_out[s], ocap);
         glob(P.ob_count[ob ^ 1])[t] = min(sh.n_ob[s], d.cap_out);
+        glob(P.start[pp])[t] = glob(P.start[pp ^ 1])[t];
+        glob(P.seg[pp])[t] = ocap;
+        if (pend) glob(P.inflow)[t] = sh.n_arr[s];  // what entered the tile this step
         sh.n_arr[s] = 0;
         sh.n_out[s] = 0;
         sh.n_ob[s] = 0;
     }
+
     // one flush of the tile's current block per step
     const double jqi = d.jq_inv;
     if (DIRECT) {
@@ -563,7 +573,8 @@ __global__ __launch_bounds__(MT) void k_settle(SimDev<R> d, int only_if_shift)
         for (int k = 0; k < N_DIR; ++k) pre[k + 1] = pre[k] + s_len[k];
         const PartBuf<R> &B = P.pb[pp];
         const int n0 = B.count[t];
-        const size_t base = (size_t)t * P.cap;
+        const size_t base = seg_start(P, pp, t);
+        const int cap = seg_slots(P, pp, t);
         int added = 0;
         for (int e0 = 0; e0 < pre[N_DIR]; e0 += MT) {
             const int e = e0 + lane;
@@ -578,7 +589,7 @@ __global__ __launch_bounds__(MT) void k_settle(SimDev<R> d, int only_if_shift)
             const unsigned long long m = __ballot(take);
             if (take) {
                 const int q = n0 + added + (int)__popcll(m & below);
-                if (q < P.cap) {
+                if (q < cap) {
                     const size_t dst = base + q;
                     B.cell[dst] = P.ob_cell[ob][o];
                     B.x[dst] = P.ob_x[ob][o];
@@ -587,12 +598,15 @@ __global__ __launch_bounds__(MT) void k_settle(SimDev<R> d, int only_if_shift)
                     B.uy[dst] = P.ob_uy[ob][o];
                     B.uz[dst] = P.ob_uz[ob][o];
                 } else {
-                    atomicOr(&d.st->err, ERR_CAPACITY);
+                    atomicOr(&d.st->err, ERR_SETTLE);
                 }
             }
             added += (int)__popcll(m);
         }
-        if (lane == 0) B.count[t] = min(n0 + added, P.cap);
+        if (lane == 0) {
+            B.count[t] = min(n0 + added, cap);
+            glob(P.inflow)[t] = added;  // what entered the tile this step
+        }
         __syncthreads();
     }
 }
@@ -1299,10 +1313,160 @@ __device__ __forceinline__ int item_slot(const SimDev<R> &d, int pp, int i)
     return 63 - load_bucket(n);
 }
 
+// Block-wide sum of v over NTO threads (every thread gets the sum).
+__device__ __forceinline__ long long block_sum_ll(long long v, long long *s_part)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) s_part[wv] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int k = 0; k < NTO / 64; ++k) t += s_part[k];
+    return t;
+}
+
+// Exclusive prefix of v over NTO threads in thread order; *total gets the sum.
+__device__ __forceinline__ long long block_prefix_ll(long long v, long long *s_part,
+                                                     long long *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    long long inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    __syncthreads();
+    if (lane == 63) s_part[wv] = inc;
+    __syncthreads();
+    long long before = 0, t = 0;
+    for (int k = 0; k < NTO / 64; ++k) {
+        before += k < wv ? s_part[k] : 0;
+        t += s_part[k];
+    }
+    *total = t;
+    return before + inc - v;
+}
+
+// Steps a layout must absorb: the layout is checked with the work order at
+// the start of every 8-step graph, so up to 15 steps can pass between checks
+// (8-step graphs and then up to 7 one-step graphs).
+constexpr int GROW_STEPS = 16;
+
+// Room tile t of species P needs in its segment to last GROW_STEPS more
+// steps: its count, plus 64, plus twice what it gained since the last check,
+// plus GROW_STEPS times what entered it from its neighbours in the last
+// step (counted by the push, or by the hand-off that appended them), and
+// with the moving window the columns loaded at the right edge meanwhile.
+template <typename R>
+__device__ __forceinline__ long long seg_need(const SimDev<R> &d, const SpDev<R> &P, int pp,
+                                              int origin, int t)
+{
+    const int tx = t % d.ntx, ty = t / d.ntx;
+    const long long cnt = glob(P.pb[pp].count)[t];
+    const long long grown = cnt - glob(P.snap)[t];
+    long long need = cnt + 64 + (grown > 0 ? 2 * grown : 0);
+    // what entered it in the last step that moved particles between tiles,
+    // for every step until the next check
+    need += (long long)GROW_STEPS * glob(P.inflow)[t];
+    if (d.window && P.density > 0.0) {
+        // storage columns entering over the next GROW_STEPS steps (at most
+        // one per step, since dt < dx)
+        const int first = (origin + d.nx) % d.nxs;
+        const int x0 = tx * TX, w = min(TX, d.nxs - x0), h = min(TY, d.ny - ty * TY);
+        int cols = 0;
+        for (int c = 0; c < GROW_STEPS; ++c) {
+            const int gx = (first + c) % d.nxs;
+            cols += gx >= x0 && gx < x0 + w;
+        }
+        need += (long long)cols * h * P.ppc_x * P.ppc_y;
+    }
+    return need;
+}
+
+// Relayout of species s's buffer ppar ^ 1 if some tile's need exceeds its
+// segment in buffer ppar: each tile gets its need rounded up to 64 slots,
+// plus a share of the rest of the pool in proportion to count + average
+// count (so that empty tiles can take in a front), at most maxseg; the
+// segments are laid out in tile order (a block-wide scan per row of NTO
+// tiles).  The next push writes its output at
+// this layout.  A pool too small for the needs raises the capacity error
+// and keeps the layout.  *s_flag must be zero, with a barrier, on entry.
+template <typename R>
+__device__ void relayout_body(const SimDev<R> &d, int s, long long *s_part, int *s_flag)
+{
+    const SpDev<R> &P = d.sp[s];
+    const gptr<const DevState> st = glob<const DevState>(d.st);
+    const int pp = st->ppar, origin = st->origin;
+    const int n = d.ntiles, rows = (n + NTO - 1) / NTO;
+    const gptr<int> needv = glob(P.need);
+    const gptr<const int> cnt_a = glob<const int>(P.pb[pp].count);
+    // tiles t = r * NTO + thread, so that every load of a row is coalesced
+    long long cnt = 0, nd = 0;
+    bool tight = false;
+    for (int r = 0; r < rows; ++r) {
+        const int t = r * NTO + (int)threadIdx.x;
+        if (t < n) {
+            const long long need = seg_need(d, P, pp, origin, t);
+            const long long base = min((long long)P.maxseg, (need + 63) / 64 * 64);
+            needv[t] = (int)base;
+            cnt += cnt_a[t];
+            nd += base;
+            tight |= need > seg_slots(P, pp, t);
+        }
+    }
+    if (tight) *s_flag = 1;  // plain store: any thread may set it
+    const long long total_cnt = block_sum_ll(cnt, s_part);
+    const long long total_need = block_sum_ll(nd, s_part);
+    if (!*s_flag) return;  // block-uniform (read after the barriers above)
+    const long long spare = (long long)P.pool - total_need;
+    if (spare < 0) {
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_or(&glob(d.st)->err, ERR_POOL, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const double avg = (double)total_cnt / n;
+    const double wsum = (double)total_cnt + avg * n;
+    long long run = 0;  // slots of the rows before (block-uniform)
+    for (int r = 0; r < rows; ++r) {
+        const int t = r * NTO + (int)threadIdx.x;
+        long long cap = 0;
+        if (t < n) {
+            const double wt = (double)cnt_a[t] + avg;
+            const long long share = wsum > 0 ? (long long)((double)spare * wt / wsum) / 64 * 64 : 0;
+            cap = min((long long)P.maxseg, (long long)needv[t] + share);
+        }
+        long long row;
+        const long long ex = block_prefix_ll(cap, s_part, &row);
+        if (t < n) {
+            glob(P.start[pp ^ 1])[t] = run + ex;
+            glob(P.seg[pp ^ 1])[t] = (int)cap;
+        }
+        run += row;
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
 {
     __shared__ int hist[64];
+    __shared__ long long s_part[NTO / 64];
+    __shared__ int s_flag;
+    // the particle layouts first (the order reads the same counts)
+    for (int s = 0; s < d.nsp; ++s) {
+        if (threadIdx.x == 0) s_flag = 0;
+        __syncthreads();
+        relayout_body(d, s, s_part, &s_flag);
+        __syncthreads();
+        // each tile's count, for the growth seen at the next check
+        const SpDev<R> &P = d.sp[s];
+        const int pp0 = glob(d.st)->ppar;
+        for (int t = threadIdx.x; t < d.ntiles; t += NTO)
+            glob(P.snap)[t] = glob(P.pb[pp0].count)[t];
+    }
     const int pp = glob(d.st)->ppar, n = d.ntiles * d.nsb;
     if (threadIdx.x < 64) hist[threadIdx.x] = 0;
     __syncthreads();
@@ -1411,7 +1575,7 @@ __device__ __forceinline__ void window_clear_body(const SimDev<R> &d, const int 
     const int t = col / TX + ty * d.ntx;
     const SpDev<R> &S = d.sp[s];
     const PartBuf<R> &P = S.pb[st->ppar];
-    const size_t base = (size_t)t * S.cap;
+    const size_t base = seg_start(S, st->ppar, t);
     const int n = P.count[t];
     int kept = 0;
     for (int p0 = 0; p0 < n; p0 += NT) {
@@ -1466,8 +1630,8 @@ __device__ __forceinline__ void window_inject_body(const SimDev<R> &d, const int
     const SpDev<R> &S = d.sp[s];
     if (!(S.density > 0.0)) return;
     const PartBuf<R> &P = S.pb[st->ppar];
-    const int cap = S.cap;
-    const size_t base = (size_t)t * cap;
+    const int cap = seg_slots(S, st->ppar, t);
+    const size_t base = seg_start(S, st->ppar, t);
     const int n0 = P.count[t];
     const int ppc = S.ppc_x * S.ppc_y;
     const int total = h * ppc;
@@ -1501,7 +1665,7 @@ __device__ __forceinline__ void window_inject_body(const SimDev<R> &d, const int
                 P.uy[o] = u[1];
                 P.uz[o] = u[2];
             } else {
-                atomicOr(&d.st->err, ERR_CAPACITY);
+                atomicOr(&d.st->err, ERR_INJECT);
             }
         }
         added += tot;
@@ -1543,8 +1707,8 @@ __global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
     const SpDev<R> &S = d.sp[s];
     const PartBuf<R> &P = S.pb[d.st->ppar];
     const int origin = d.st->origin, nshift = d.st->nshift;
-    const int cap = S.cap;
-    const size_t base = (size_t)t * cap;
+    const int cap = seg_slots(S, d.st->ppar, t);
+    const size_t base = seg_start(S, d.st->ppar, t);
     const int ncell = w * h, ppc = S.ppc_x * S.ppc_y;
     const int total = ncell * ppc;
     int added = 0;
@@ -1581,7 +1745,7 @@ __global__ __launch_bounds__(NT) void k_load(SimDev<R> d, int s)
                 P.uy[o] = u[1];
                 P.uz[o] = u[2];
             } else {
-                atomicOr(&d.st->err, ERR_CAPACITY);
+                atomicOr(&d.st->err, ERR_LOAD);
             }
         }
         added += tot;
@@ -1607,7 +1771,7 @@ __global__ __launch_bounds__(NT) void k_rho(SimDev<R> d)
         const SpDev<R> &S = d.sp[s];
         const PartBuf<R> &P = S.pb[d.st->ppar];
         const int n = P.count[t];
-        const size_t base = (size_t)t * S.cap;
+        const size_t base = seg_start(S, d.st->ppar, t);
         const R qp = S.qp * d.jq;  // carries the fixed-point scale
         for (int p = threadIdx.x; p < n; p += NT) {
             const int c = P.cell[base + p];
@@ -1749,7 +1913,7 @@ __global__ __launch_bounds__(NT) void k_diag_ke(SimDev<R> d)
         const SpDev<R> &S = d.sp[s];
         const PartBuf<R> &P = S.pb[d.st->ppar];
         const int n = P.count[t];
-        const size_t base = (size_t)t * S.cap;
+        const size_t base = seg_start(S, d.st->ppar, t);
         const double mp = (double)S.qp / (double)S.qm;
         double ke = 0;
         for (int p = threadIdx.x; p < n; p += NT) {

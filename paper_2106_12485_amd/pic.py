@@ -328,7 +328,7 @@ class Simulation:
     def layout(self):
         a = np.zeros(7, dtype=np.int64)
         _check(lib().pic_layout(self._h, a.ctypes.data_as(_LLP), 7))
-        keys = ("tile_x", "tile_y", "ntx", "nty", "nx_storage", "cap", "cap_out")
+        keys = ("tile_x", "tile_y", "ntx", "nty", "nx_storage", "pool", "cap_out")
         return dict(zip(keys, (int(v) for v in a)))
 
 

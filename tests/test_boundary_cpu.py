@@ -51,11 +51,11 @@ def test_mem_bytes_of_the_workloads(libpic):
         # at least the particle state of the initial load
         assert n > w.n_particles_initial() * 24
         assert mem_bytes(w, fp64=True) > n
-    # clouds: 2 species x 2 particle buffers x 4096 tiles x (3 x 16 ppc x 256)
-    # slots x 24 B dominate (about 4.8 GB); the outboxes (a quarter of the
-    # slots at 25 B) add about 1.3 GB
+    # clouds: 2 species x 2 particle buffers x (2 x 8,388,608 + 64 x 4096)
+    # slots x 24 B dominate (about 1.64 GB); the outboxes (a quarter of a full
+    # tile, 1024 slots per tile, at 25 B) add about 0.42 GB
     n = mem_bytes(clouds1024())
-    assert 6.0e9 < n < 6.5e9
+    assert 2.0e9 < n < 2.4e9
 
 
 def test_validation_rejects_bad_configurations(libpic):
