@@ -1284,34 +1284,9 @@ __device__ __forceinline__ void yee_s_body(const SimDev<R> &d, const int blk)
     }
 }
 
-// Work order of the push: its work items (tiles, or a tile's species
-// blocks) by decreasing particle count, in 64 buckets two per octave,
-// heaviest first.  Within a bucket the order is that of the atomic claims;
-// any order is a permutation of the items, which is all the push needs.
-// One block of NTO threads.
+// Work order of the push and the particle layouts: one block of NTO
+// threads, launched at most every 8 pushes (k_order below).
 constexpr int NTO = 1024;
-
-__device__ __forceinline__ int load_bucket(int n)
-{
-    // 2 floor(log2(n + 1)) + the next bit: 0 .. 63, monotone in n
-    const unsigned v = (unsigned)n + 1u;
-    const int e = 31 - __clz(v);
-    const int half = e > 0 ? (int)((v >> (e - 1)) & 1u) : 0;
-    return min(63, 2 * e + half);
-}
-
-template <typename R>
-__device__ __forceinline__ int item_slot(const SimDev<R> &d, int pp, int i)
-{
-    // bucket index of item i, heaviest first
-    const int t = i / d.nsb;
-    int n = 0;
-    if (d.nsb > 1)
-        n = glob(d.sp[i % d.nsb].pb[pp].count)[t];
-    else
-        for (int s = 0; s < d.nsp; ++s) n += glob(d.sp[s].pb[pp].count)[t];
-    return 63 - load_bucket(n);
-}
 
 // Block-wide sum of v over NTO threads (every thread gets the sum).
 __device__ __forceinline__ long long block_sum_ll(long long v, long long *s_part)
@@ -1449,12 +1424,65 @@ __device__ void relayout_body(const SimDev<R> &d, int s, long long *s_part, int 
     }
 }
 
+// The push's block b takes work item order[b].  The items are sorted,
+// heaviest first, into 64 load buckets, two per octave, with the bucket
+// edges a quarter octave off the powers of two (a tile of 2^k particles, the
+// usual initial load, sits mid-bucket, so sampling noise does not split such
+// tiles over two buckets).  The sort is stable: within a bucket the items
+// keep their tile order.  Blocks go to the 8 XCDs in turn (b % 8), each XCD
+// with an L2 of its own, and the sorted list is dealt to them in chunks of
+// ORDER_CHUNK consecutive items, so each XCD starts on the heavy items and
+// works along runs of neighbouring tiles, which share field and current
+// halos.
+constexpr int ORDER_CHUNK = 8;
+
+// Block of sorted position p (a bijection of [0, n)): chunks of ORDER_CHUNK
+// positions dealt to the 8 XCDs in turn; the last, partial round ranked by
+// (offset in chunk, chunk).
+__device__ __forceinline__ int order_block(int p, int n)
+{
+    constexpr int G = ORDER_CHUNK, RND = 8 * ORDER_CHUNK;
+    const int full = (n / RND) * RND;
+    if (p < full) {
+        // rounds of 8 chunks, the XCDs taking them forwards in even rounds
+        // and backwards in odd ones (a heavy chunk, then a light one)
+        const int rd = p / RND, c = (p / G) % 8, x = rd & 1 ? 7 - c : c;
+        return 8 * (rd * G + p % G) + x;
+    }
+    const int T = n - full, q = p - full, x = q / G, o = q % G;
+    const int nch = (T + G - 1) / G;
+    int rank = 0;
+    for (int c = 0; c < nch; ++c) {
+        const int sz = min(G, T - c * G);
+        rank += min(sz, o) + (c < x && sz > o ? 1 : 0);
+    }
+    return full + rank;
+}
+
+template <typename R>
+__device__ __forceinline__ int item_load(const SimDev<R> &d, int pp, int i)
+{
+    const int t = i / d.nsb;
+    if (d.nsb > 1) return glob(d.sp[i % d.nsb].pb[pp].count)[t];
+    int n = 0;
+    for (int s = 0; s < d.nsp; ++s) n += glob(d.sp[s].pb[pp].count)[t];
+    return n;
+}
+
+__device__ __forceinline__ int load_bucket(int w)
+{
+    // 63 - floor(2 log2(w + 1) + 1/2): 0 for the heaviest, monotone
+    const int k = (int)floorf(2.0f * __log2f((float)w + 1.0f) + 0.5f);
+    return 63 - min(63, max(0, k));
+}
+
 template <typename R>
 __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
 {
-    __shared__ int hist[64];
     __shared__ long long s_part[NTO / 64];
     __shared__ int s_flag;
+    __shared__ int s_wc[NTO / 64][64];
+    __shared__ int s_base[64];
     // the particle layouts first (the order reads the same counts)
     for (int s = 0; s < d.nsp; ++s) {
         if (threadIdx.x == 0) s_flag = 0;
@@ -1468,24 +1496,57 @@ __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
             glob(P.snap)[t] = glob(P.pb[pp0].count)[t];
     }
     const int pp = glob(d.st)->ppar, n = d.ntiles * d.nsb;
-    if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+    const int rows = (n + NTO - 1) / NTO;
+    if (threadIdx.x < 64) s_base[threadIdx.x] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += NTO) atomicAdd(&hist[item_slot(d, pp, i)], 1);
+    for (int i = threadIdx.x; i < n; i += NTO) atomicAdd(&s_base[load_bucket(item_load(d, pp, i))], 1);
     __syncthreads();
     if (threadIdx.x < 64) {
-        // exclusive prefix over the buckets (one wavefront)
-        const int v = hist[threadIdx.x];
-        int inc = v;
+        // exclusive prefix over the buckets, in one wavefront
+        const int c = s_base[threadIdx.x];
+        int v = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(inc, o, 64);
-            if ((int)threadIdx.x >= o) inc += u;
+            const int u = __shfl_up(v, o, 64);
+            if ((int)threadIdx.x >= o) v += u;
         }
-        hist[threadIdx.x] = inc - v;
+        s_base[threadIdx.x] = v - c;
     }
-    __syncthreads();
+    // stable counting sort, one row of NTO items at a time: the rank within
+    // the wavefront by ballots over the buckets present in it, then the
+    // counts of the wavefronts before
     const gptr<int> order = glob(d.order);
-    for (int i = threadIdx.x; i < n; i += NTO) order[atomicAdd(&hist[item_slot(d, pp, i)], 1)] = i;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r = 0; r < rows; ++r) {
+        const int i = r * NTO + (int)threadIdx.x;
+        s_wc[wv][lane] = 0;
+        __syncthreads();
+        const int k = i < n ? load_bucket(item_load(d, pp, i)) : -1;
+        int rank = 0;
+        unsigned long long todo = __ballot(k >= 0);
+        while (todo) {
+            const int lead = __ffsll((long long)todo) - 1;
+            const int kc = __shfl(k, lead, 64);
+            const unsigned long long m = __ballot(k == kc);
+            if (k == kc) rank = (int)__popcll(m & below);
+            if (lane == lead) s_wc[wv][kc] = (int)__popcll(m);
+            todo &= ~m;
+        }
+        __syncthreads();
+        if (k >= 0) {
+            int pos = s_base[k] + rank;
+            for (int w2 = 0; w2 < wv; ++w2) pos += s_wc[w2][k];
+            order[order_block(pos, n)] = i;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            int add = 0;
+            for (int w2 = 0; w2 < NTO / 64; ++w2) add += s_wc[w2][threadIdx.x];
+            s_base[threadIdx.x] += add;
+        }
+        __syncthreads();
+    }
 }
 
 template <typename R, int RF>
