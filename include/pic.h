@@ -373,13 +373,17 @@ typedef struct {
     const volatile int *cancel; /* NULL, or n flags the caller may set from another
                             thread while pic_serve runs: cancel[i] != 0 cancels
                             request i at the next chunk boundary */
+    long long max_particles; /* batched: a queued request joins a non-empty running
+                            set only while the set's initial particle loads, its
+                            own included, stay within this; the queue is then
+                            admitted strictly in arrival order (<= 0: no limit) */
 } pic_serve_opts;
 
 /* Serve n requests in real time (the work is the paper's cycle of Sec. 2.2 on
  * many independent simulations; no paper passage defines the loop itself): a
  * request is queued at its arrival time, admitted (first fit, in arrival
  * order) when its pic_mem_bytes fits in the free part of `arena` (the HBM
- * budget), initialised on a stream of its own while the running set keeps
+ * budget) and, with max_particles, the running set's load allows, initialised on a stream of its own while the running set keeps
  * stepping, stepped with the running set in chunks of at most chunk_steps
  * (shared launches, pic_batch_step; a set of one runs its own step graph;
  * with rate_ratio > 1, cheaper requests take extra steps per chunk in shared

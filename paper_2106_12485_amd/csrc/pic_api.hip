@@ -1682,6 +1682,18 @@ class ArenaAlloc {
     std::map<size_t, size_t> free_;
 };
 
+// Particles a configuration loads at initialisation (0 if it is invalid).
+long long initial_particles(const pic_cfg *c)
+{
+    Layout L;
+    if (layout(c, &L) != PIC_OK || !c->load) return 0;
+    long long n = 0;
+    for (int s = 0; s < c->n_species; ++s)
+        if (c->sp[s].density > 0.0)
+            for (long long v : load_counts(c, L.nxs, L.ntx, L.nty, s)) n += v;
+    return n;
+}
+
 struct Active {
     int req;
     pic_sim *sim;
@@ -1746,6 +1758,10 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
         auto now = [&] {
             return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         };
+        // initial particle loads, for the running set's limit
+        std::vector<long long> load(n, 0);
+        if (opts->batched && opts->max_particles > 0)
+            for (int i = 0; i < n; ++i) load[i] = initial_particles(&reqs[i].cfg);
         std::vector<int> queue;
         std::vector<Active> active;
         std::vector<pic_sim *> sims;
@@ -1767,6 +1783,11 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
                     ++done;
                     queue.erase(queue.begin() + qi);
                     continue;
+                }
+                if (opts->batched && opts->max_particles > 0 && !active.empty()) {
+                    long long running = load[r];
+                    for (const Active &a : active) running += load[a.req];
+                    if (running > opts->max_particles) break;  // in arrival order
                 }
                 const long long off = alloc.take(need);
                 if (off < 0) {

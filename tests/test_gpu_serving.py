@@ -251,3 +251,36 @@ def test_multirate_chunks_give_the_same_results():
         assert np.array_equal(a["diag"]["n_particles"], b["diag"]["n_particles"])
     print("multirate done_s lockstep", [round(x["done_s"], 4) for x in lock],
           "multirate", [round(x["done_s"], 4) for x in multi], flush=True)
+
+
+def test_particle_limit_admits_in_order_and_keeps_results():
+    """max_particles: a request joins a running set only while the set's
+    initial particle loads, its own included, stay within the limit, and the
+    queue is admitted strictly in arrival order.  Checked on the recorded
+    admission and retirement times; every request still ends bitwise as in
+    serving without the limit."""
+    reqs = [(0.0, w, 30) for _, w in serving_requests(n_requests=6, grids=(64, 128),
+                                                      ppcs=((2, 2), (4, 4)), steps=30)]
+    loads = []
+    for _, w, _ in reqs:
+        s = Simulation(w)
+        loads.append(sum(s.count(k) for k in range(len(w.species))))
+        del s
+    free = serve(reqs, 4 << 30, batched=True, chunk_steps=5)["results"]
+    for lim in (2 * int(np.median(loads)), 1):
+        res = serve(reqs, 4 << 30, batched=True, chunk_steps=5, max_particles=lim)["results"]
+        admits = [r["admit_s"] for r in res]
+        assert admits == sorted(admits), admits  # arrival order (all arrive at 0)
+        for i, r in enumerate(res):
+            assert r["status"] == 0
+            running = [j for j, q in enumerate(res)
+                       if j != i and q["admit_s"] <= r["admit_s"] < q["done_s"]]
+            if running:
+                assert loads[i] + sum(loads[j] for j in running) <= lim, (i, running, lim)
+            a, b = r["diag"], free[i]["diag"]
+            assert a["step"] == b["step"] == 30
+            assert a["e_energy"] == b["e_energy"] and a["b_energy"] == b["b_energy"]
+            assert np.array_equal(a["n_particles"], b["n_particles"])
+        if lim == 1:  # every request alone, one after the other
+            for i in range(1, len(res)):
+                assert res[i]["admit_s"] >= res[i - 1]["done_s"]
