@@ -235,9 +235,11 @@ def cpu_coverage():
         k = nsteps or w.steps
         pushes = 0.0
         t0 = time.perf_counter()
-        for _ in range(k):
+        for i in range(k):
             pushes += sum(o.count(j) for j in range(len(w.species)))
             o.step(1)
+            if (i + 1) % 20 == 0:
+                progress("oracle %s, %d thread(s): step %d of %d" % (name, threads, i + 1, k))
         dt = time.perf_counter() - t0
         rows.append(dict(workload=name, steps=k, threads=threads, seconds=round(dt, 2),
                          pushes=int(pushes), pushes_per_s=pushes / dt))
