@@ -1368,7 +1368,8 @@ __device__ __forceinline__ long long seg_need(const SimDev<R> &d, const SpDev<R>
 // segments are laid out in tile order (a block-wide scan per row of NTO
 // tiles).  The next push writes its output at
 // this layout.  A pool too small for the needs raises the capacity error
-// and keeps the layout.  *s_flag must be zero, with a barrier, on entry.
+// and keeps the layout.  Every tile's count is kept as its snapshot for the
+// next check.  *s_flag must be zero, with a barrier, on entry.
 template <typename R>
 __device__ void relayout_body(const SimDev<R> &d, int s, long long *s_part, int *s_flag)
 {
@@ -1378,18 +1379,37 @@ __device__ void relayout_body(const SimDev<R> &d, int s, long long *s_part, int 
     const int n = d.ntiles, rows = (n + NTO - 1) / NTO;
     const gptr<int> needv = glob(P.need);
     const gptr<const int> cnt_a = glob<const int>(P.pb[pp].count);
-    // tiles t = r * NTO + thread, so that every load of a row is coalesced
+    // tiles t = r * NTO + thread, so that every load of a row is coalesced;
+    // rows in groups of RG whose loads all go out before the group's stores
+    constexpr int RG = 4;
     long long cnt = 0, nd = 0;
     bool tight = false;
-    for (int r = 0; r < rows; ++r) {
-        const int t = r * NTO + (int)threadIdx.x;
-        if (t < n) {
-            const long long need = seg_need(d, P, pp, origin, t);
-            const long long base = min((long long)P.maxseg, (need + 63) / 64 * 64);
-            needv[t] = (int)base;
-            cnt += cnt_a[t];
-            nd += base;
-            tight |= need > seg_slots(P, pp, t);
+    for (int r0 = 0; r0 < rows; r0 += RG) {
+        long long need[RG];
+        int cn[RG], sl[RG];
+#pragma unroll
+        for (int k = 0; k < RG; ++k) {
+            const int t = (r0 + k) * NTO + (int)threadIdx.x;
+            need[k] = 0;
+            cn[k] = 0;
+            sl[k] = 0;
+            if (r0 + k < rows && t < n) {
+                need[k] = seg_need(d, P, pp, origin, t);
+                cn[k] = cnt_a[t];
+                sl[k] = seg_slots(P, pp, t);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RG; ++k) {
+            const int t = (r0 + k) * NTO + (int)threadIdx.x;
+            if (r0 + k < rows && t < n) {
+                const long long base = min((long long)P.maxseg, (need[k] + 63) / 64 * 64);
+                needv[t] = (int)base;
+                glob(P.snap)[t] = cn[k];  // the count, for the growth seen at the next check
+                cnt += cn[k];
+                nd += base;
+                tight |= need[k] > sl[k];
+            }
         }
     }
     if (tight) *s_flag = 1;  // plain store: any thread may set it
@@ -1483,23 +1503,43 @@ __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
     __shared__ int s_flag;
     __shared__ int s_wc[NTO / 64][64];
     __shared__ int s_base[64];
+    // bucket of every item while they fit (read once, used by both passes)
+    constexpr int KB_MAX = 16384;
+    __shared__ unsigned char s_kb[KB_MAX];
     // the particle layouts first (the order reads the same counts)
     for (int s = 0; s < d.nsp; ++s) {
         if (threadIdx.x == 0) s_flag = 0;
         __syncthreads();
         relayout_body(d, s, s_part, &s_flag);
         __syncthreads();
-        // each tile's count, for the growth seen at the next check
-        const SpDev<R> &P = d.sp[s];
-        const int pp0 = glob(d.st)->ppar;
-        for (int t = threadIdx.x; t < d.ntiles; t += NTO)
-            glob(P.snap)[t] = glob(P.pb[pp0].count)[t];
     }
     const int pp = glob(d.st)->ppar, n = d.ntiles * d.nsb;
     const int rows = (n + NTO - 1) / NTO;
     if (threadIdx.x < 64) s_base[threadIdx.x] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += NTO) atomicAdd(&s_base[load_bucket(item_load(d, pp, i))], 1);
+    for (int i0 = 0; i0 < n; i0 += 4 * NTO) {
+        int kk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k * NTO + (int)threadIdx.x;
+            kk[k] = i < n ? load_bucket(item_load(d, pp, i)) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k * NTO + (int)threadIdx.x;
+            if (kk[k] >= 0 && n <= KB_MAX) s_kb[i] = (unsigned char)kk[k];
+            // one LDS atomic per bucket present in the wavefront (most items
+            // share a bucket: one atomic per lane would serialise on it)
+            unsigned long long todo = __ballot(kk[k] >= 0);
+            while (todo) {
+                const int lead = __ffsll((long long)todo) - 1;
+                const int kc = __shfl(kk[k], lead, 64);
+                const unsigned long long m = __ballot(kk[k] == kc);
+                if ((int)(threadIdx.x & 63) == lead) atomicAdd(&s_base[kc], (int)__popcll(m));
+                todo &= ~m;
+            }
+        }
+    }
     __syncthreads();
     if (threadIdx.x < 64) {
         // exclusive prefix over the buckets, in one wavefront
@@ -1522,7 +1562,7 @@ __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
         const int i = r * NTO + (int)threadIdx.x;
         s_wc[wv][lane] = 0;
         __syncthreads();
-        const int k = i < n ? load_bucket(item_load(d, pp, i)) : -1;
+        const int k = i >= n ? -1 : n <= KB_MAX ? (int)s_kb[i] : load_bucket(item_load(d, pp, i));
         int rank = 0;
         unsigned long long todo = __ballot(k >= 0);
         while (todo) {
@@ -2074,12 +2114,13 @@ template <> struct PushWaves<double> { static constexpr int n = 4; };
 // which shortens the launch most when the particles pile up in a few tiles.
 //
 // Block b takes work item d.order[b] (a tile, or a tile's species block).
-// Blocks are dispatched in about the order of their index, and the order
-// lists the items by decreasing particle count (k_order rewrites it every
-// 8 steps), so heavy tiles start first and the launch ends on light ones:
-// the GPU form of the paper's over-decomposition with dynamic distribution
-// of regions to workers (Sec. 3.2, 4.3), where a region that holds many
-// particles must not start last.
+// Blocks are dispatched in about the order of their index, and k_order
+// (at most every 8 steps) sorts the items heaviest first in load buckets and
+// deals them to the XCDs in runs of neighbours, so heavy tiles start first
+// and the launch ends on light ones: the GPU form of the paper's
+// over-decomposition with dynamic distribution of regions to workers
+// (Sec. 3.2, 4.3), where a region that holds many particles must not start
+// last.
 template <typename R, int BT>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(PushWaves<R>::n))) void
 k_push_deposit(SimDev<R> d)
