@@ -83,6 +83,10 @@ def parse():
                     help="only time the oracle over the measurement plan's coverage (the "
                          "64x64 and 2000x256 runs in full, 20 steps of the two clouds, 64 "
                          "steps of the 8000x512 run in the parallel-for mode) and print it")
+    ap.add_argument("--clock-warmup-s", type=float, default=0.3,
+                    help="untimed, before the measured run: seconds of steps of a throwaway "
+                         "copy of the workload, so that the GPU's clocks have left their idle "
+                         "state (0 = skip; skipped with --profile-only)")
     ap.add_argument("--phase-step", type=int, default=500,
                     help="first step of the second timed window (0 = skip it)")
     ap.add_argument("--profile-only", action="store_true",
@@ -127,6 +131,27 @@ def copy_peak_gbs(mib=1024, reps=5):
     del a, b
     torch.cuda.empty_cache()
     return 2.0 * n * 4 / (best * 1e-3) / 1e9
+
+
+def clock_warmup(w, fp64, deposit, seconds):
+    """Step a throwaway copy of workload w for `seconds` of wall time, then
+    free it.  A GPU that was idle runs its first tens of milliseconds of
+    work at lower clocks (the two-cloud push took 250-260 us per launch over
+    the first steps after a cold start, ~210 us on a warm GPU), so the
+    measured run starts after this.  Returns the steps done."""
+    import torch
+    from paper_2106_12485_amd import Simulation
+    tmp = Simulation(w, fp64=fp64, deposit=deposit)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        tmp.step(16)
+        torch.cuda.synchronize()
+        n += 16
+    tmp.close()
+    del tmp
+    torch.cuda.empty_cache()
+    return n
 
 
 def copy_calibration(mib):
@@ -295,6 +320,10 @@ def main():
         print(json.dumps(dict(cpu_coverage=cpu_coverage(), cores=host_threads())))
         return
     w = WORKLOADS[args.workload]()
+    warm_steps = 0
+    if args.clock_warmup_s > 0 and not args.profile_only:
+        warm_steps = clock_warmup(w, args.fp64, args.deposit, args.clock_warmup_s)
+        progress("clock warm-up done (%d steps of a throwaway copy)" % warm_steps)
     sim = Simulation(w, fp64=args.fp64, deposit=args.deposit)
     nparts = sum(sim.count(k) for k in range(len(w.species)))
     stream = sim.stream
@@ -352,6 +381,9 @@ def main():
                     species=len(w.species), ppc_per_species=w.species[0].ppc[0] *
                     w.species[0].ppc[1], dt=w.dt, filter_passes=w.filter_passes,
                     moving_window=w.moving_window, deposit=args.deposit),
+        clock_warmup=dict(seconds=args.clock_warmup_s if warm_steps else 0.0, steps=warm_steps,
+                          what="untimed steps of a throwaway copy of the workload before the "
+                               "measured run (GPU clocks out of their idle state)"),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=(None if args.workload != "clouds_1024x1024" or args.fp64
