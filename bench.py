@@ -165,7 +165,8 @@ def copy_calibration(mib):
     print(json.dumps(dict(copy_bytes=n * 4, launches=5)))
 
 
-def serving_leg(nreq, budget_gb, chunk=10, rate_ratio=4, max_particles=1 << 24):
+def serving_leg(nreq, budget_gb, chunk=10, rate_ratio=4, max_particles=1 << 24,
+                lone_particles=1 << 22):
     """Stream of independent periodic plasmas (grids 64^2..512^2, 4/16/64 ppc,
     thermal or two-stream, 200 steps each) served within an HBM budget: every
     request present at t = 0, then Poisson arrivals at 0.5, 1 and 2 times the
@@ -173,8 +174,11 @@ def serving_leg(nreq, budget_gb, chunk=10, rate_ratio=4, max_particles=1 << 24):
     batches and in multi-rate batches (cheaper requests take up to rate_ratio
     times as many steps per chunk).  The batches admit a request only while
     the running set's initial loads stay within max_particles (the two-cloud
-    run's 16.8M particles already fill the GPU), in arrival order.  Request
-    latency p50/p99 and throughput for every mode at every load."""
+    run's 16.8M particles already fill the GPU), in arrival order, or within
+    lone_particles when no other request waits behind it (at light load a
+    request that finds the GPU busy then waits instead of slowing a large
+    one down).  Request latency p50/p99 and throughput for every mode at
+    every load."""
     from inputs import serving_requests
     from paper_2106_12485_amd import serve
     budget = int(budget_gb * 2 ** 30)
@@ -203,10 +207,11 @@ def serving_leg(nreq, budget_gb, chunk=10, rate_ratio=4, max_particles=1 << 24):
         return dict(
             one_at_a_time=summary(serve(reqs, budget, batched=False, chunk_steps=chunk), reqs),
             batched_lockstep=summary(serve(reqs, budget, batched=True, chunk_steps=chunk,
-                                           max_particles=max_particles), reqs),
+                                           max_particles=max_particles,
+                                           lone_particles=lone_particles), reqs),
             batched_multirate=summary(serve(reqs, budget, batched=True, chunk_steps=chunk,
-                                            rate_ratio=rate_ratio,
-                                            max_particles=max_particles), reqs))
+                                            rate_ratio=rate_ratio, max_particles=max_particles,
+                                            lone_particles=lone_particles), reqs))
 
     serve(reqs0[:4], budget, batched=True, chunk_steps=chunk)  # warm-up
     t0 = modes(reqs0)
@@ -215,6 +220,7 @@ def serving_leg(nreq, budget_gb, chunk=10, rate_ratio=4, max_particles=1 << 24):
     out = dict(workload="serving stream: %d periodic plasmas, grids 64..512^2, ppc 4/16/64, "
                         "200 steps each, HBM budget %.0f GB" % (nreq, budget_gb),
                chunk_steps=chunk, rate_ratio=rate_ratio, max_particles=max_particles,
+               lone_particles=lone_particles,
                one_at_a_time_rate_per_s=rate,
                all_at_t0=t0)
     rng = np.random.default_rng(0x5EED0003)

@@ -377,6 +377,9 @@ typedef struct {
                             set only while the set's initial particle loads, its
                             own included, stay within this; the queue is then
                             admitted strictly in arrival order (<= 0: no limit) */
+    long long lone_particles; /* batched, with max_particles: the same limit for a
+                            request that no other queued request waits behind
+                            (<= 0: max_particles) */
 } pic_serve_opts;
 
 /* Serve n requests in real time (the work is the paper's cycle of Sec. 2.2 on

@@ -1787,7 +1787,12 @@ extern "C" int pic_serve(const pic_request *reqs, int n, void *arena, size_t are
                 if (opts->batched && opts->max_particles > 0 && !active.empty()) {
                     long long running = load[r];
                     for (const Active &a : active) running += load[a.req];
-                    if (running > opts->max_particles) break;  // in arrival order
+                    // no backlog behind this request: the lone limit
+                    const bool lone = qi + 1 == queue.size();
+                    const long long cap = lone && opts->lone_particles > 0
+                                              ? opts->lone_particles
+                                              : opts->max_particles;
+                    if (running > cap) break;  // in arrival order
                 }
                 const long long off = alloc.take(need);
                 if (off < 0) {

@@ -66,7 +66,7 @@ class Result(C.Structure):
 class ServeOpts(C.Structure):
     _fields_ = [("batched", C.c_int), ("chunk_steps", C.c_int), ("max_batch", C.c_int),
                 ("rate_ratio", C.c_int), ("cancel", C.POINTER(C.c_int)),
-                ("max_particles", C.c_longlong)]
+                ("max_particles", C.c_longlong), ("lone_particles", C.c_longlong)]
 
 
 class PicError(RuntimeError):
@@ -387,13 +387,16 @@ def batch_step_static(sims, nsteps=1, stream=None):
 
 
 def serve(requests, budget_bytes, batched=True, chunk_steps=10, max_batch=0, device="cuda",
-          max_step_records=1 << 16, rate_ratio=1, cancel_flags=None, max_particles=0):
+          max_step_records=1 << 16, rate_ratio=1, cancel_flags=None, max_particles=0,
+          lone_particles=0):
     """Serve `requests` = [(arrival_s, workload, nsteps[, cancel_s]), ...]
     through the native continuous-batching loop within an HBM budget of
     budget_bytes.  cancel_flags: None, or an int32 numpy array of one flag per
     request that another thread may set while this call runs (nonzero cancels
     the request).  max_particles (batched): a request joins a running set only
-    while the set's initial particle loads stay within it (0: no limit).
+    while the set's initial particle loads stay within it (0: no limit);
+    lone_particles: that limit for a request with no other queued request
+    behind it (0: max_particles).
     Returns per-request times / diagnostics and the per-step batch times."""
     import torch
     n = len(requests)
@@ -411,7 +414,7 @@ def serve(requests, budget_bytes, batched=True, chunk_steps=10, max_batch=0, dev
         assert cancel_flags.flags["C_CONTIGUOUS"]
         flags = cancel_flags.ctypes.data_as(C.POINTER(C.c_int))
     opts = ServeOpts(int(bool(batched)), int(chunk_steps), int(max_batch), int(rate_ratio), flags,
-                     int(max_particles))
+                     int(max_particles), int(lone_particles))
     arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
     step_ms = np.zeros(max_step_records)
     nsteps_out = C.c_longlong(0)

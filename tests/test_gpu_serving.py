@@ -284,3 +284,14 @@ def test_particle_limit_admits_in_order_and_keeps_results():
         if lim == 1:  # every request alone, one after the other
             for i in range(1, len(res)):
                 assert res[i]["admit_s"] >= res[i - 1]["done_s"]
+    # lone_particles: the last request has no other queued request behind it,
+    # so it waits until the running set is empty (a limit of one particle)
+    lim = 2 * int(np.median(loads))
+    res = serve(reqs, 4 << 30, batched=True, chunk_steps=5, max_particles=lim,
+                lone_particles=1)["results"]
+    last = res[-1]
+    assert all(q["done_s"] <= last["admit_s"] for q in res[:-1]), [
+        (q["admit_s"], q["done_s"]) for q in res]
+    for r, f in zip(res, free):
+        assert r["status"] == 0
+        assert r["diag"]["e_energy"] == f["diag"]["e_energy"]
