@@ -10,6 +10,9 @@
   (tile, block entry) pairs that land on the cell.
 - The streaming field kernels' strips own every cell exactly once.
 - The particle hand-off delivers every leaver to exactly one tile.
+- The push's work order (`k_order`, `order_block`): a stable counting sort of
+  the items into load buckets, heaviest first, dealt to the XCDs in chunks;
+  every item gets exactly one block.
 """
 import itertools
 import random
@@ -259,3 +262,93 @@ def test_commutative_colours_never_share_a_cell_where_the_library_accepts_the_gr
     assert accepted > 50 and rejected > 5
     # the two grids with a 2-cell last tile that overlapped before they were refused
     assert colour_overlaps(50, 32) and colour_overlaps(18, 20)
+
+
+# ---------------------------------------------------------------------------
+# the push's work order: items sorted into load buckets (stable), dealt to the
+# 8 XCDs in chunks of consecutive items (k_order, order_block)
+# ---------------------------------------------------------------------------
+ORDER_CHUNK = 8
+
+
+def order_block(p, n, g=ORDER_CHUNK):
+    """Block of sorted position p: full rounds of 8 chunks of g positions go to
+    the XCDs (block % 8) forwards in even rounds, backwards in odd ones; the
+    last, partial round is ranked by (offset in chunk, chunk)."""
+    rnd = 8 * g
+    full = (n // rnd) * rnd
+    if p < full:
+        rd, c = p // rnd, (p // g) % 8
+        x = 7 - c if rd & 1 else c
+        return 8 * (rd * g + p % g) + x
+    t, q = n - full, p - full
+    x, o = q // g, q % g
+    rank = 0
+    for c in range((t + g - 1) // g):
+        sz = min(g, t - c * g)
+        rank += min(sz, o) + (1 if (c < x and sz > o) else 0)
+    return full + rank
+
+
+def load_bucket(w):
+    """63 - floor(2 log2(w + 1) + 1/2), clamped to 0..63: heaviest first."""
+    import math
+    k = math.floor(2.0 * math.log2(w + 1.0) + 0.5)
+    return 63 - min(63, max(0, k))
+
+
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 63, 64, 65, 511, 512, 513, 1024, 2048, 4095,
+                               4096, 4100, 16384, 16391])
+def test_order_block_is_a_bijection(n):
+    assert sorted(order_block(p, n) for p in range(n)) == list(range(n))
+
+
+def test_order_block_deals_chunks_to_xcds_in_snake_rounds():
+    n = 8 * ORDER_CHUNK * 4
+    for p in range(n):
+        b = order_block(p, n)
+        rd, c = p // (8 * ORDER_CHUNK), (p // ORDER_CHUNK) % 8
+        assert b % 8 == (7 - c if rd & 1 else c)
+        # consecutive positions of a chunk go to consecutive blocks of one XCD
+        if p % ORDER_CHUNK:
+            assert order_block(p - 1, n) == b - 8
+
+
+def test_bucket_order_is_heaviest_first_and_stable():
+    rng = random.Random(5)
+    loads = [rng.choice([0, 3, 4000, 4096, 4200, 8192, 16000, 70000]) for _ in range(3000)]
+    n = len(loads)
+    keys = [load_bucket(w) for w in loads]
+    # the counting sort of k_order: exclusive prefix over buckets, then ranks in
+    # item order
+    base = [0] * 64
+    for k in keys:
+        base[k] += 1
+    acc = 0
+    for k in range(64):
+        base[k], acc = acc, acc + base[k]
+    pos = []
+    for k in keys:
+        pos.append(base[k])
+        base[k] += 1
+    order = [None] * n
+    for i, p in enumerate(pos):
+        order[order_block(p, n)] = i
+    assert sorted(order) == list(range(n))
+    by_pos = sorted(range(n), key=lambda i: pos[i])
+    # heavier buckets first; within a bucket, item order
+    for a, b in zip(by_pos, by_pos[1:]):
+        assert keys[a] < keys[b] or (keys[a] == keys[b] and a < b)
+    # a load of 2^k sits mid-bucket: +-15% stays in its bucket
+    for k in range(6, 20):
+        w = 2 ** k
+        assert load_bucket(int(w * 0.87)) == load_bucket(w) == load_bucket(int(w * 1.15))
+
+
+def test_the_order_model_uses_the_device_constants():
+    import os
+    src = open(os.path.join(os.path.dirname(__file__), "..", "paper_2106_12485_amd", "csrc",
+                            "pic_kernels.hip")).read()
+    assert "constexpr int ORDER_CHUNK = %d;" % ORDER_CHUNK in src
+    assert "floorf(2.0f * __log2f((float)w + 1.0f) + 0.5f)" in src
+    assert "return 8 * (rd * G + p % G) + x;" in src
