@@ -101,7 +101,7 @@ typedef struct {
 } pic_laser_cfg;
 
 typedef struct {
-    int nx, ny;          /* cells; each >= 2 and <= 32767, and n % 16 != 1 */
+    int nx, ny;          /* cells; each >= 2 and <= 32767 */
     double lx, ly;       /* box size; dx = lx/nx, dy = ly/ny */
     double dt;           /* must satisfy dt < 1/sqrt(1/dx^2 + 1/dy^2) */
     int moving_window;   /* 1: the box follows +x at c (x not periodic) */
@@ -126,7 +126,8 @@ typedef struct {
                               colours, one colour per launch, add their
                               current straight into J, no two neighbours at
                               once; no fold.  Needs a periodic box with an
-                              even number of 16-cell tiles along each axis. */
+                              even number of 16-cell tiles along each axis,
+                              the last at least 3 cells wide. */
 } pic_cfg;
 
 /* Diagnostics in FP64 (stage a9).  Energies are integrals over the box:

@@ -159,9 +159,6 @@ int layout(const pic_cfg *c, Layout *L)
         return fail(PIC_E_ARG, "nx and ny must be in [2, 32767]");
     if (!(c->lx > 0) || !(c->ly > 0) || !(c->dt > 0))
         return fail(PIC_E_ARG, "lx, ly and dt must be positive");
-    if (c->ny % TY == 1) return fail(PIC_E_ARG, "ny % 16 == 1 would leave a one-cell tile");
-    if (!c->moving_window && c->nx % TX == 1)
-        return fail(PIC_E_ARG, "nx % 16 == 1 would leave a one-cell tile");
     if (c->n_species < 0 || c->n_species > PIC_MAX_SPECIES)
         return fail(PIC_E_ARG, "n_species must be in [0, 4]");
     if (c->filter_passes < 0 || c->filter_passes + (c->filter_compensate ? 1 : 0) > MAX_FR ||
@@ -193,9 +190,10 @@ int layout(const pic_cfg *c, Layout *L)
     // last tile, across the periodic seam), so their blocks are disjoint only
     // if that tile is at least 3 cells wide: every middle tile is 16 wide, the
     // last one n % 16.
-    if (c->deposit_mode == 1 && (L->nxs % TX == 2 || c->ny % TY == 2))
+    if (c->deposit_mode == 1 && (L->nxs % TX == 1 || L->nxs % TX == 2 || c->ny % TY == 1 ||
+                                 c->ny % TY == 2))
         return fail(PIC_E_ARG, "the commutative deposit needs the last tile along each axis "
-                               "to be at least 3 cells wide (n % 16 != 2)");
+                               "to be at least 3 cells wide (n % 16 not 1 or 2)");
     L->ntiles = L->ntx * L->nty;
     L->rs = c->fp64 ? 8 : 4;
     L->plane = (size_t)L->nxs * c->ny;
@@ -287,6 +285,8 @@ void describe(const pic_cfg *c, const Layout &L, char *a, SimDev<R> *d)
     d->nxs = L.nxs;
     d->ntx = L.ntx;
     d->nty = L.nty;
+    d->rx = fold_reach(L.nxs, TX);
+    d->ry = fold_reach(c->ny, TY);
     d->ntiles = L.ntiles;
     d->window = c->moving_window ? 1 : 0;
     d->nsp = c->n_species;

@@ -128,6 +128,8 @@ template <typename R>
 struct SimDev {
     int nx, ny, nxs;
     int ntx, nty, ntiles;
+    int rx, ry;       // tiles the fold searches on each side along x, y: 1, or 2
+                      // where the last tile is one cell wide (see fold_reach)
     int window, nsp, cap_out;
     int push_bt;      // threads per single-simulation push block: NTP or NTP_BIG
     int nsb;          // push blocks per tile: 1, or one per species (blk then holds
@@ -256,6 +258,33 @@ __device__ __forceinline__ double rsqrt1(double x) { return 1.0 / sqrt(x); }
 
 __device__ __forceinline__ int pack_cell(int ix, int iy) { return ix | (iy << 16); }
 __device__ __forceinline__ int cell_x(int c) { return c & 0xffff; }
+
+// Tiles the fold searches on each side along an axis of n cells.  A tile's
+// current block spans its cells plus one guard below and two above, so the
+// entries on a cell come from the tile's own block and its neighbours' --
+// unless the last tile along the axis is one cell wide: the guards of the
+// tile before it then reach over it into the next tile, two tiles away.
+__host__ __device__ constexpr int fold_reach(int n, int size) { return n % size == 1 ? 2 : 1; }
+
+// Offset of cell l of tile t within the block of tile t + o (periodic, n
+// cells, tiles of `size` cells with a shorter last one).
+__device__ __forceinline__ int span_off(int l, int o, int t, int n, int size)
+{
+    const int nt = (n + size - 1) / size;
+    int p = l;
+    if (o < 0) {
+        for (int k = 1; k <= -o; ++k) {
+            const int a = wrapi(t - k, nt);
+            p += min(size, n - a * size);
+        }
+    } else {
+        for (int k = 0; k < o; ++k) {
+            const int a = wrapi(t + k, nt);
+            p -= min(size, n - a * size);
+        }
+    }
+    return p;
+}
 __device__ __forceinline__ int cell_y(int c) { return c >> 16; }
 
 // window coordinate of storage column gx (>= nx means the gap)

@@ -635,15 +635,15 @@ __device__ __forceinline__ void fold_body(const SimDev<R> &d, const int t, int n
         const int lx = k % w, ly = k / w;
         const int gx = x0 + lx, gy = y0 + ly;
         R a0 = 0, a1 = 0, a2 = 0;
-        for (int oy = -1; oy <= 1; ++oy) {
+        for (int oy = -d.ry; oy <= d.ry; ++oy) {
             const int tyn = wrapi(ty + oy, d.nty);
             const int hn = min(TY, d.ny - tyn * TY);
-            const int py = oy == 0 ? ly : (oy < 0 ? ly + hn : ly - h);
+            const int py = span_off(ly, oy, ty, d.ny, TY);
             if (py < -1 || py >= hn + 2) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
+            for (int ox = -d.rx; ox <= d.rx; ++ox) {
                 const int txn = wrapi(tx + ox, d.ntx);
                 const int wn = min(TX, d.nxs - txn * TX);
-                const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
+                const int px = span_off(lx, ox, tx, d.nxs, TX);
                 if (px < -1 || px >= wn + 2) continue;
                 const gptr<const R> b = glob<const R>(
                     d.blk + (size_t)(txn + tyn * d.ntx) * 3 * BP + (px + 1) + (py + 1) * PX);
@@ -910,7 +910,7 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
         for (int g = 0; g < NSB; ++g) sum += q[(size_t)g * 3 * BP];
         return (R)fx_value(sum, d.jq_inv);
     };
-    if (h == TY && w >= 3) {
+    if (d.rx == 1 && d.ry == 1 && h == TY && w >= 3) {
         const int txl = wrapi(tx - 1, d.ntx), txr = wrapi(tx + 1, d.ntx);
         const int tyl = wrapi(ty - 1, d.nty), tyu = wrapi(ty + 1, d.nty);
         const int wl = min(TX, d.nxs - txl * TX), hl = min(TY, d.ny - tyl * TY);
@@ -966,15 +966,15 @@ __device__ __forceinline__ void fold_s_body(const SimDev<R> &d, const int blk, R
     }
     for (int ly = ly0; ly < ly1; ++ly) {
         R a[3] = {0, 0, 0};
-        for (int oy = -1; oy <= 1; ++oy) {
+        for (int oy = -d.ry; oy <= d.ry; ++oy) {
             const int tyn = wrapi(ty + oy, d.nty);
             const int hn = min(TY, d.ny - tyn * TY);
-            const int py = oy == 0 ? ly : (oy < 0 ? ly + hn : ly - h);
+            const int py = span_off(ly, oy, ty, d.ny, TY);
             if (py < -1 || py >= hn + 2) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
+            for (int ox = -d.rx; ox <= d.rx; ++ox) {
                 const int txn = wrapi(tx + ox, d.ntx);
                 const int wn = min(TX, d.nxs - txn * TX);
-                const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
+                const int px = span_off(lx, ox, tx, d.nxs, TX);
                 if (px < -1 || px >= wn + 2) continue;
                 const size_t b = img(txn, tyn);
 #pragma unroll
@@ -1021,7 +1021,7 @@ __device__ __forceinline__ void fold_cell(const SimDev<R> &d, int gx, int gy, R 
     const gptr<const R> blk = glob<const R>(d.blk);
     auto img = [&](int ia, int ib) { return (size_t)(ia + ib * d.ntx) * 3 * BP; };
     a[0] = a[1] = a[2] = R(0);
-    if (h == TY && w >= 3) {
+    if (d.rx == 1 && d.ry == 1 && h == TY && w >= 3) {
         const int txl = wrapi(tx - 1, d.ntx), txr = wrapi(tx + 1, d.ntx);
         const int wl = min(TX, d.nxs - txl * TX);
         const int xo = lx < 2 ? -1 : (lx == w - 1 ? 1 : 0);
@@ -1047,15 +1047,15 @@ __device__ __forceinline__ void fold_cell(const SimDev<R> &d, int gx, int gy, R 
         if (ly == TY - 1) level(wrapi(ty + 1, d.nty), 0);
         return;
     }
-    for (int oy = -1; oy <= 1; ++oy) {
+    for (int oy = -d.ry; oy <= d.ry; ++oy) {
         const int tyn = wrapi(ty + oy, d.nty);
         const int hn = min(TY, d.ny - tyn * TY);
-        const int py = oy == 0 ? ly : (oy < 0 ? ly + hn : ly - h);
+        const int py = span_off(ly, oy, ty, d.ny, TY);
         if (py < -1 || py >= hn + 2) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
+        for (int ox = -d.rx; ox <= d.rx; ++ox) {
             const int txn = wrapi(tx + ox, d.ntx);
             const int wn = min(TX, d.nxs - txn * TX);
-            const int px = ox == 0 ? lx : (ox < 0 ? lx + wn : lx - w);
+            const int px = span_off(lx, ox, tx, d.nxs, TX);
             if (px < -1 || px >= wn + 2) continue;
             const size_t b = img(txn, tyn) + (px + 1) + (py + 1) * PX;
 #pragma unroll

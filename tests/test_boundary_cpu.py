@@ -79,7 +79,12 @@ def test_validation_rejects_bad_configurations(libpic):
     c = pic.make_cfg(w)
     c.nx, c.lx, c.ny, c.ly = 32767, 3276.7, 32767, 3276.7
     assert libpic.pic_mem_bytes(C.byref(c)) > 0
-    assert "16" in bad(nx=33)
+    # a one-cell last tile is accepted (the fold then searches two tiles each
+    # way), except by the commutative deposit, whose colours would overlap
+    c = pic.make_cfg(w)
+    c.nx, c.lx, c.ny, c.ly = 33, 3.3, 49, 4.9
+    assert libpic.pic_mem_bytes(C.byref(c)) > 0
+    assert "3 cells" in bad(deposit_mode=1, nx=49, lx=4.9)
     assert "n_species" in bad(n_species=5)
     assert "filter" in bad(filter_passes=0, filter_compensate=1)
     assert "filter" in bad(filter_passes=4, filter_compensate=1)

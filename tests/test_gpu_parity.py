@@ -120,6 +120,22 @@ CASES = {
     # a window narrower than a tile: the shift takes its separate launches
     "window_12x20": (two_species(12, 20, 0.24, 4.0, dt=0.014, moving_window=True,
                                  filter_passes=1, filter_compensate=True), False, False),
+    # one-cell last tiles (n % 16 == 1): the fold searches two tiles each way;
+    # along x (fold inside the Yee launch), along y with the compensator (the
+    # separate fold launch), both with two tiles per axis (wrap), FP64, the
+    # window, and tiles with one push block per species (64-bit slices)
+    "thin_x_33x20": (two_species(33, 20, 3.3, 2.0, filter_passes=1), False, False),
+    "thin_y_20x33_comp": (two_species(20, 33, 2.0, 3.3, filter_passes=1,
+                                      filter_compensate=True), False, False),
+    "thin_both_17x17": (two_species(17, 17, 1.7, 1.7, filter_passes=1), False, True),
+    "thin_49x33_fp64": (two_species(49, 33, 4.9, 3.3, filter_passes=1), True, False),
+    "thin_window_60x17": (two_species(60, 17, 1.2, 3.4, dt=0.014, moving_window=True,
+                                      filter_passes=1, filter_compensate=True), False, False),
+    "thin_big_tiles_33x17": (Workload("big", 33, 17, 3.3, 1.7, 0.07, 1,
+                                      [SpeciesSpec(-1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3),
+                                       SpeciesSpec(1.0, 1.0, ppc=(16, 16), uth=(0.3,) * 3,
+                                                   ufl=(0.0, 0.0, 0.5))],
+                                      filter_passes=1), False, False),
 }
 
 
@@ -159,6 +175,8 @@ SPARSE = {
                                     filter_compensate=True), (300, 200), False),
     "max_nx_window_32767x18": (two_species(32767, 18, 655.34, 3.6, dt=0.014, moving_window=True,
                                            filter_passes=1), (300, 200), False),
+    # one-cell last tiles along both axes, then 5 more steps of hand-offs
+    "thin_17x33": (two_species(17, 33, 1.7, 3.3, filter_passes=1), (400, 300), False),
 }
 
 

@@ -35,23 +35,45 @@ def brute(nxs, ny, gx, gy):
     return sorted((a, cx, b, cy) for (a, cx), (b, cy) in itertools.product(xs, ys))
 
 
-def general(nxs, ny, gx, gy):
-    """The 3 x 3 neighbour search, in its (oy, ox) order."""
+def reach(n, size):
+    """Tiles searched on each side along an axis of n cells: one, or two when
+    the last tile is one cell wide (the guards of the tile before it then
+    reach over it)."""
+    return 2 if n % size == 1 else 1
+
+
+def span_off(l, o, t, n, size):
+    """Offset of cell l of tile t within the block of tile t + o (periodic)."""
+    nt = (n + size - 1) // size
+    ext = lambda a: min(size, n - size * a)
+    p = l
+    if o < 0:
+        for k in range(1, -o + 1):
+            p += ext((t - k) % nt)
+    else:
+        for k in range(o):
+            p -= ext((t + k) % nt)
+    return p
+
+
+def general(nxs, ny, gx, gy, rx=None, ry=None):
+    """The neighbour search over (2 reach + 1)^2 tiles, in its (oy, ox) order."""
     ntx, nty = (nxs + TX - 1) // TX, (ny + TY - 1) // TY
+    rx = reach(nxs, TX) if rx is None else rx
+    ry = reach(ny, TY) if ry is None else ry
     tx, ty = gx // TX, gy // TY
     lx, ly = gx - TX * tx, gy - TY * ty
-    w, h = min(TX, nxs - TX * tx), min(TY, ny - TY * ty)
     out = []
-    for oy in (-1, 0, 1):
+    for oy in range(-ry, ry + 1):
         tyn = (ty + oy) % nty
         hn = min(TY, ny - TY * tyn)
-        py = ly if oy == 0 else (ly + hn if oy < 0 else ly - h)
+        py = span_off(ly, oy, ty, ny, TY)
         if py < -1 or py >= hn + 2:
             continue
-        for ox in (-1, 0, 1):
+        for ox in range(-rx, rx + 1):
             txn = (tx + ox) % ntx
             wn = min(TX, nxs - TX * txn)
-            px = lx if ox == 0 else (lx + wn if ox < 0 else lx - w)
+            px = span_off(lx, ox, tx, nxs, TX)
             if px < -1 or px >= wn + 2:
                 continue
             out.append((txn, px + 1, tyn, py + 1))
@@ -59,12 +81,13 @@ def general(nxs, ny, gx, gy):
 
 
 def fast(nxs, ny, gx, gy):
-    """The path for a full-height tile at least 3 columns wide (None otherwise)."""
+    """The path for a full-height tile at least 3 columns wide on a grid with
+    no one-cell tile (None otherwise)."""
     ntx, nty = (nxs + TX - 1) // TX, (ny + TY - 1) // TY
     tx, ty = gx // TX, gy // TY
     lx, ly = gx - TX * tx, gy - TY * ty
     w, h = min(TX, nxs - TX * tx), min(TY, ny - TY * ty)
-    if not (h == TY and w >= 3):
+    if not (reach(nxs, TX) == 1 and reach(ny, TY) == 1 and h == TY and w >= 3):
         return None
     txl, txr = (tx - 1) % ntx, (tx + 1) % ntx
     wl = min(TX, nxs - TX * txl)
@@ -90,12 +113,12 @@ def fast(nxs, ny, gx, gy):
 
 
 def shapes():
-    # sizes the library accepts: no one-cell tile along either axis
-    ok = [n for n in range(2, 70) if n % TX != 1]
     rng = random.Random(7)
     yield from [(4, 4), (2, 2), (3, 70), (18, 20), (34, 18), (32, 32), (16, 16), (48, 34)]
+    # one-cell last tiles along x, y or both, and two-tile grids that wrap
+    yield from [(17, 20), (33, 16), (49, 33), (20, 17), (17, 17), (65, 49), (33, 2), (2, 33)]
     for _ in range(40):
-        yield rng.choice(ok), rng.choice(ok)
+        yield rng.randrange(2, 70), rng.randrange(2, 70)
     # moving-window storage widths are multiples of 16
     yield from [(32, 20), (64, 9), (80, 34)]
 
@@ -112,13 +135,14 @@ def test_fold_selects_exactly_the_covering_block_entries(nxs, ny):
                 assert f == g, (gx, gy)
 
 
-def test_a_one_cell_tile_would_be_missed():
-    # why a grid may not leave a one-cell tile: the guard columns of the tile
-    # two to the left then reach over it, beyond the 3 x 3 neighbour search
-    nxs, ny = 33, 16
-    misses = [(gx, gy) for gy in range(ny) for gx in range(nxs)
-              if sorted(general(nxs, ny, gx, gy)) != brute(nxs, ny, gx, gy)]
-    assert misses
+def test_a_one_cell_tile_needs_the_wider_search():
+    # why a grid that leaves a one-cell tile searches two tiles each way: the
+    # guard columns of the tile two to the left reach over the one-cell tile,
+    # beyond a 3 x 3 neighbour search
+    for nxs, ny in ((33, 16), (16, 33)):
+        misses = [(gx, gy) for gy in range(ny) for gx in range(nxs)
+                  if sorted(general(nxs, ny, gx, gy, rx=1, ry=1)) != brute(nxs, ny, gx, gy)]
+        assert misses
 
 
 # ---------------------------------------------------------------------------
