@@ -101,7 +101,8 @@ typedef struct {
 } pic_laser_cfg;
 
 typedef struct {
-    int nx, ny;          /* cells; each >= 2 and <= 32767 */
+    int nx, ny;          /* cells; each >= 2 and <= 65535 (nx <= 65518 with the
+                            moving window) */
     double lx, ly;       /* box size; dx = lx/nx, dy = ly/ny */
     double dt;           /* must satisfy dt < 1/sqrt(1/dx^2 + 1/dy^2) */
     int moving_window;   /* 1: the box follows +x at c (x not periodic) */

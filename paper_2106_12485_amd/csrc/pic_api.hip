@@ -155,8 +155,13 @@ bool layout_from_counts(const std::vector<long long> &cnt, long long pool, long 
 int layout(const pic_cfg *c, Layout *L)
 {
     if (!c) return fail(PIC_E_ARG, "cfg is NULL");
-    if (c->nx < 2 || c->ny < 2 || c->nx > 32767 || c->ny > 32767)
-        return fail(PIC_E_ARG, "nx and ny must be in [2, 32767]");
+    // cell indices are packed in 16 bits per axis (storage columns with the
+    // moving window: nx plus the gap, rounded up to the tile width)
+    if (c->nx < 2 || c->ny < 2 || c->nx > 65535 || c->ny > 65535)
+        return fail(PIC_E_ARG, "nx and ny must be in [2, 65535]");
+    if (c->moving_window && (c->nx + TX + 2 + TX - 1) / TX * TX > 65536)
+        return fail(PIC_E_ARG, "with the moving window nx must be at most 65518 (the storage "
+                               "width adds an 18-cell gap, rounded to the tile width)");
     if (!(c->lx > 0) || !(c->ly > 0) || !(c->dt > 0))
         return fail(PIC_E_ARG, "lx, ly and dt must be positive");
     if (c->n_species < 0 || c->n_species > PIC_MAX_SPECIES)
@@ -791,7 +796,7 @@ int do_set_particles(pic_sim *s, const SimDev<R> &d, int sp, long long n, const 
         R xr = (R)x[k], yr = (R)y[k];
         if (xr >= R(1)) xr = std::nextafter(R(1), R(0));  // rounding must stay in [0, 1)
         if (yr >= R(1)) yr = std::nextafter(R(1), R(0));
-        hc[q] = gx | (iy[k] << 16);
+        hc[q] = (int)((unsigned)gx | ((unsigned)iy[k] << 16));
         hx[q] = xr;
         hy[q] = yr;
         hux[q] = (R)ux[k];
@@ -855,7 +860,7 @@ int do_get_particles(pic_sim *s, const SimDev<R> &d, int sp, long long cap, long
     for (long long k = 0; k < n; ++k) {
         const int gx = hc[k] & 0xffff;
         ix[k] = s->cfg.moving_window ? (gx - origin + L.nxs) % L.nxs : gx;
-        iy[k] = hc[k] >> 16;
+        iy[k] = (int)((unsigned)hc[k] >> 16);
         x[k] = hx[k];
         y[k] = hy[k];
         ux[k] = hux[k];

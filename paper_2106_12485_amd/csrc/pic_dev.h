@@ -89,7 +89,7 @@ __device__ __forceinline__ int dir_index(int dtx, int dty)
 
 template <typename R>
 struct PartBuf {
-    int *cell;        // packed storage cell: ix | iy << 16
+    int *cell;        // packed storage cell: ix | iy << 16 (16 bits each, unsigned)
     R *x, *y, *ux, *uy, *uz;
     int *count;       // particles per tile
 };
@@ -256,7 +256,10 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsqrt1(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt1(double x) { return 1.0 / sqrt(x); }
 
-__device__ __forceinline__ int pack_cell(int ix, int iy) { return ix | (iy << 16); }
+__device__ __forceinline__ int pack_cell(int ix, int iy)
+{
+    return (int)((unsigned)ix | ((unsigned)iy << 16));
+}
 __device__ __forceinline__ int cell_x(int c) { return c & 0xffff; }
 
 // Tiles the fold searches on each side along an axis of n cells.  A tile's
@@ -285,7 +288,7 @@ __device__ __forceinline__ int span_off(int l, int o, int t, int n, int size)
     }
     return p;
 }
-__device__ __forceinline__ int cell_y(int c) { return c >> 16; }
+__device__ __forceinline__ int cell_y(int c) { return (int)((unsigned)c >> 16); }
 
 // window coordinate of storage column gx (>= nx means the gap)
 __device__ __forceinline__ int window_col(int gx, int origin, int nxs)

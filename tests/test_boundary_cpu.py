@@ -73,12 +73,17 @@ def test_validation_rejects_bad_configurations(libpic):
 
     assert "Courant" in bad(dt=0.1 / math.sqrt(2) * 1.0001)
     assert "nx" in bad(nx=1)
-    # cell indices are packed in 16 bits each: 32767 is the largest extent
-    assert "32767" in bad(nx=32768, lx=3276.8)
-    assert "32767" in bad(ny=32768, ly=3276.8)
+    # cell indices are packed in 16 bits each (unsigned): 65535 is the largest
+    # extent, 65518 with the moving window (its storage adds an 18-cell gap)
+    assert "65535" in bad(nx=65536, lx=6553.6)
+    assert "65535" in bad(ny=65536, ly=6553.6)
     c = pic.make_cfg(w)
-    c.nx, c.lx, c.ny, c.ly = 32767, 3276.7, 32767, 3276.7
+    c.nx, c.lx, c.ny, c.ly = 65535, 6553.5, 65535, 6553.5
     assert libpic.pic_mem_bytes(C.byref(c)) > 0
+    c = pic.make_cfg(w)
+    c.nx, c.lx, c.moving_window = 65518, 6551.8, 1
+    assert libpic.pic_mem_bytes(C.byref(c)) > 0
+    assert "65518" in bad(nx=65519, lx=6551.9, moving_window=1)
     # a one-cell last tile is accepted (the fold then searches two tiles each
     # way), except by the commutative deposit, whose colours would overlap
     c = pic.make_cfg(w)

@@ -168,12 +168,13 @@ SPARSE = {
     "three_particles_window_60x20": (two_species(60, 20, 1.2, 4.0, dt=0.014, moving_window=True,
                                                  filter_passes=1, filter_compensate=True),
                                      (2, 1), False),
-    # the largest grid extents (32767 cells: cell indices use 16 bits each,
-    # ragged last tile of 15), a few hundred particles
-    "max_nx_32767x18": (two_species(32767, 18, 3276.7, 1.8, filter_passes=1), (300, 200), False),
-    "max_ny_18x32767": (two_species(18, 32767, 1.8, 3276.7, filter_passes=1,
+    # the largest grid extents (65535 cells: cell indices use 16 bits each,
+    # unsigned; ragged last tile of 15 cells), a few hundred particles; the
+    # window's storage adds an 18-cell gap, so its largest nx is 65518
+    "max_nx_65535x18": (two_species(65535, 18, 6553.5, 1.8, filter_passes=1), (300, 200), False),
+    "max_ny_18x65535": (two_species(18, 65535, 1.8, 6553.5, filter_passes=1,
                                     filter_compensate=True), (300, 200), False),
-    "max_nx_window_32767x18": (two_species(32767, 18, 655.34, 3.6, dt=0.014, moving_window=True,
+    "max_nx_window_65518x18": (two_species(65518, 18, 1310.36, 3.6, dt=0.014, moving_window=True,
                                            filter_passes=1), (300, 200), False),
     # one-cell last tiles along both axes, then 5 more steps of hand-offs
     "thin_17x33": (two_species(17, 33, 1.7, 3.3, filter_passes=1), (400, 300), False),
