@@ -151,9 +151,14 @@ def test_batched_members_match_the_oracle(halos):
     import os
     from parity_util import compare_state, oracle_mirror
     ws = _serving_like(0x5EED7000 if halos == "shared" else 0x5EED7100)
+    # and a grid whose last tiles are one cell wide along both axes (the fold
+    # then searches two tiles each way)
+    ws.append(Workload("thermal_49x33_ppc4", 49, 33, 4.9, 3.3, 0.07, 10,
+                       [SpeciesSpec(-1.0, 1.0, ppc=(2, 2), uth=(0.2,) * 3)], seed=0x5EED7200))
     if halos == "mixed":
         ws[1].filter_passes, ws[1].filter_compensate = 1, True
         ws[2].filter_passes = 3
+        ws[4].filter_passes = 2
     sims = [Simulation(w) for w in ws]
     ntiles = sum(s.layout()["ntx"] * s.layout()["nty"] for s in sims)
     b = Batch(len(sims), ntiles)
