@@ -214,7 +214,6 @@ struct PushShared {
     int n_arr[MAX_SP];            // arrivals found per species
     int n_out[MAX_SP];            // stayers written per species
     int n_ob[MAX_SP];             // leavers written per species
-    int item;                     // work item of a persistent block
 };
 
 // Zero the per-species counters (before the barrier that precedes a tile).
