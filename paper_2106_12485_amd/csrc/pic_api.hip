@@ -529,7 +529,7 @@ constexpr int GRAPH_STEPS = GRAPH_STEPS_N;
 template <typename R>
 int enqueue_push(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool order)
 {
-    if (order && !d.direct) {
+    if (order) {  // the colour-phased pushes take no order, but need the layouts
         const int rc = timed(s, 6, st, [&] { return Launch<R>::order(d, st); });
         if (rc) return rc;
     }
@@ -959,7 +959,7 @@ int do_step(pic_sim *s, const SimDev<R> &d, int nsteps, hipStream_t st)
     for (int n = 0; n < nsteps % GRAPH_STEPS; ++n) {
         // one-step graphs hold no work order: launch one directly when due
         if (s->since_order >= GRAPH_STEPS) {
-            if (!d.direct) HIPCHK(Launch<R>::order(d, st));
+            HIPCHK(Launch<R>::order(d, st));
             s->since_order = 0;
         }
         HIPCHK(hipGraphLaunch(s->gexec, st));
@@ -1319,6 +1319,23 @@ void batch_layout(int max_sims, long long max_tiles, size_t *o_table, size_t *o_
     *total = o;
 }
 
+// Before each batched step: the particle layouts of every member (one
+// launch over the descriptor table) once any member has taken GRAPH_STEPS
+// pushes since its last check, the cadence of pic_step; then every member
+// counts the step.
+hipError_t batch_layouts(pic_sim *const *sims, int n, const SimDev<float> *table, hipStream_t st)
+{
+    bool due = false;
+    for (int i = 0; i < n; ++i) due |= sims[i]->since_order >= GRAPH_STEPS;
+    if (due) {
+        const hipError_t e = Launch<float>::layout_b(table, n, st);
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < n; ++i) sims[i]->since_order = 0;
+    }
+    for (int i = 0; i < n; ++i) ++sims[i]->since_order;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1475,7 +1492,10 @@ int pic_batch_step(pic_batch *b, pic_sim *const *sims, int n, int nsteps, void *
                 b->rf = rf;
             }
         }
-        for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(b->gexec, st));
+        for (int k = 0; k < nsteps; ++k) {
+            HIPCHK(batch_layouts(sims, n, b->d_table, st));
+            HIPCHK(hipGraphLaunch(b->gexec, st));
+        }
         return PIC_OK;
     });
 }
@@ -1634,9 +1654,11 @@ int pic_batch_step_static(pic_sim *const *sims, int n, int nsteps, void *stream)
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_lists, dim3(64), dim3(256), 0, st, work, fwork, ywork, lists);
         HIPCHK(hipGetLastError());
-        for (int k = 0; k < nsteps; ++k)
+        for (int k = 0; k < nsteps; ++k) {
+            HIPCHK(batch_layouts(sims, n, table, st));
             HIPCHK(launch_batch_step<float>(table, bd, (int)tot[0], st, rf, (int)tot[1],
                                             (int)tot[2]));
+        }
         return PIC_OK;
     });
 }

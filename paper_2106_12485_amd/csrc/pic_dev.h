@@ -70,6 +70,7 @@ struct DevState {
     int opar;         // outbox written by the last push
     int pend;         // 1: that outbox holds leavers not yet in any tile
     int blocks_done;  // blocks of the running push launch that finished
+    int relay;        // 1: a push left some tile's segment short (relayout at the step end)
 };
 
 // Particle hand-off between tiles.  A push reads its tile from particle
@@ -331,6 +332,8 @@ template <typename R> struct Launch {
     static hipError_t push_deposit(const SimDev<R> &d, hipStream_t s);
     // rewrite the push's work order, heaviest items first
     static hipError_t order(const SimDev<R> &d, hipStream_t s);
+    // the particle layouts of the n simulations of a batch's descriptor table
+    static hipError_t layout_b(const SimDev<R> *ds, int n, hipStream_t s);
     // only_if_shift: skip unless the last step shifted the moving window;
     // unpend = false leaves clearing the pending flag to the window launch
     static hipError_t settle(const SimDev<R> &d, hipStream_t s, bool only_if_shift = false,

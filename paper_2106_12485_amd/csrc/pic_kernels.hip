@@ -286,6 +286,13 @@ __device__ __forceinline__ void gather_arrivals(const SimDev<R> &d, const SpDev<
     }
 }
 
+// Steps of inflow a segment must still have room for after a push; with
+// fewer free slots the push asks for a relayout at the end of the step.
+// Between the periodic checks a tile's inflow can rise several-fold (dense
+// bunches of a two-stream instability sweeping into it), faster than room
+// reserved from the inflow seen at the last check covers.
+constexpr int RELAY_STEPS = 4;
+
 // One tile (t) of one push: g selects the species when d.nsb > 1 species
 // blocks share a tile (this block then pushes species g only and leaves its
 // current block as exact 64-bit sums in slice g of the tile; the fold adds
@@ -493,7 +500,12 @@ __device__ __forceinline__ void push_tile(const SimDev<R> &d, const int t, const
         const int s = s0 + (int)threadIdx.x;
         const SpDev<R> &P = d.sp[s];
         const int ocap = seg_slots(P, pp ^ 1, t);
-        glob(P.pb[pp ^ 1].count)[t] = min(sh.n_out[s], ocap);
+        const int kept = min(sh.n_out[s], ocap);
+        // fewer free slots than RELAY_STEPS more steps of this step's
+        // inflow: the step end lays the segments out anew (a plain store of
+        // 1, so any block may make it)
+        if (kept + RELAY_STEPS * sh.n_arr[s] + 64 > ocap) glob(d.st)->relay = 1;
+        glob(P.pb[pp ^ 1].count)[t] = kept;
         glob(P.ob_count[ob ^ 1])[t] = min(sh.n_ob[s], d.cap_out);
         glob(P.start[pp])[t] = glob(P.start[pp ^ 1])[t];
         glob(P.seg[pp])[t] = ocap;
@@ -1495,23 +1507,34 @@ __device__ __forceinline__ int load_bucket(int w)
     return 63 - min(63, max(0, k));
 }
 
+// The particle layouts of every species of one simulation (relayout_body).
+// One block of NTO threads; ends with a barrier.
 template <typename R>
-__global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
+__device__ void layouts_body(const SimDev<R> &d)
 {
     __shared__ long long s_part[NTO / 64];
     __shared__ int s_flag;
-    __shared__ int s_wc[NTO / 64][64];
-    __shared__ int s_base[64];
-    // bucket of every item while they fit (read once, used by both passes)
-    constexpr int KB_MAX = 16384;
-    __shared__ unsigned char s_kb[KB_MAX];
-    // the particle layouts first (the order reads the same counts)
     for (int s = 0; s < d.nsp; ++s) {
         if (threadIdx.x == 0) s_flag = 0;
         __syncthreads();
         relayout_body(d, s, s_part, &s_flag);
         __syncthreads();
     }
+}
+
+// The particle layouts, then, with write_order, the push's work order.  One
+// block of NTO threads.
+template <typename R>
+__device__ __forceinline__ void order_body(const SimDev<R> &d, bool write_order)
+{
+    __shared__ int s_wc[NTO / 64][64];
+    __shared__ int s_base[64];
+    // bucket of every item while they fit (read once, used by both passes)
+    constexpr int KB_MAX = 16384;
+    __shared__ unsigned char s_kb[KB_MAX];
+    // the particle layouts first (the order reads the same counts)
+    layouts_body(d);
+    if (!write_order) return;
     const int pp = glob(d.st)->ppar, n = d.ntiles * d.nsb;
     const int rows = (n + NTO - 1) / NTO;
     if (threadIdx.x < 64) s_base[threadIdx.x] = 0;
@@ -1586,6 +1609,21 @@ __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
         }
         __syncthreads();
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
+{
+    order_body(d, true);
+}
+
+// The particle layouts of every simulation of a batch, one block each.  The
+// batched push takes its work from a (simulation, tile) list, so the
+// simulations' own work orders are left as they are.
+template <typename R>
+__global__ __launch_bounds__(NTO) void k_layout_b(const SimDev<R> *__restrict__ ds)
+{
+    order_body(ds[blockIdx.x], false);
 }
 
 template <typename R, int RF>
@@ -2212,11 +2250,18 @@ __global__ __launch_bounds__(NT) void k_yee(SimDev<R> d)
 }
 
 // A Yee launch is short, so its blocks' completion counts would pile up on one
-// address; the step end runs as a one-thread launch instead.
+// address; the step end runs as a one-block launch instead.  When a push of
+// the step asked for it (DevState::relay), the block then lays out the
+// particle segments of every species anew for the next push.
 template <typename R>
-__global__ void k_step_end(SimDev<R> d)
+__global__ __launch_bounds__(NTO) void k_step_end(SimDev<R> d)
 {
+    const bool relay = glob<const DevState>(d.st)->relay != 0;
     if (threadIdx.x == 0) step_end_body(d);
+    if (!relay) return;  // block-uniform
+    __syncthreads();     // the layouts read the new window origin
+    layouts_body(d);
+    if (threadIdx.x == 0) d.st->relay = 0;
 }
 
 template <typename R>
@@ -2227,10 +2272,32 @@ __global__ __launch_bounds__(NT) void k_yee_b(const SimDev<R> *__restrict__ ds,
     if (batch_item(b, &it)) yee_body(ds[it.x], it.y);
 }
 
+// The batch's step end: one thread per simulation, then the relayouts that
+// pushes asked for, one simulation after another (most steps ask for none).
 template <typename R>
-__global__ void k_step_end_b(const SimDev<R> *__restrict__ ds, const BatchDev *__restrict__ b)
+__global__ __launch_bounds__(NTO) void k_step_end_b(const SimDev<R> *__restrict__ ds,
+                                                    const BatchDev *__restrict__ b)
 {
-    for (int i = threadIdx.x; i < b->nsim; i += blockDim.x) step_end_body(ds[i]);
+    __shared__ int s_n;
+    __shared__ int s_list[NTO];
+    const int n = b->nsim;
+    for (int i0 = 0; i0 < n; i0 += NTO) {
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        const int i = i0 + (int)threadIdx.x;
+        if (i < n) {
+            if (glob<const DevState>(ds[i].st)->relay) s_list[atomicAdd(&s_n, 1)] = i;
+            step_end_body(ds[i]);
+        }
+        __syncthreads();
+        const int m = s_n;
+        for (int k = 0; k < m; ++k) {
+            const SimDev<R> &d = ds[s_list[k]];
+            layouts_body(d);
+            if (threadIdx.x == 0) d.st->relay = 0;
+        }
+        __syncthreads();  // s_n and s_list are reused
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2260,6 +2327,13 @@ template <typename R>
 hipError_t Launch<R>::order(const SimDev<R> &d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_order<R>, dim3(1), dim3(NTO), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::layout_b(const SimDev<R> *ds, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_layout_b<R>, dim3(n), dim3(NTO), 0, s, ds);
     return hipGetLastError();
 }
 
@@ -2344,7 +2418,7 @@ hipError_t Launch<R>::yee(const SimDev<R> &d, hipStream_t s)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_step_end<R>, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_step_end<R>, dim3(1), dim3(NTO), 0, s, d);
     return hipGetLastError();
 }
 
@@ -2432,7 +2506,7 @@ hipError_t launch_batch_step(const SimDev<R> *ds, const BatchDev *b, int grid, h
         hipLaunchKernelGGL(k_filter_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
         hipLaunchKernelGGL(k_yee_b<R>, dim3(grid), dim3(NT), 0, s, ds, b);
     }
-    hipLaunchKernelGGL(k_step_end_b<R>, dim3(1), dim3(64), 0, s, ds, b);
+    hipLaunchKernelGGL(k_step_end_b<R>, dim3(1), dim3(NTO), 0, s, ds, b);
     return hipGetLastError();
 }
 

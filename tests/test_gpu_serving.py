@@ -300,3 +300,41 @@ def test_particle_limit_admits_in_order_and_keeps_results():
     for r, f in zip(res, free):
         assert r["status"] == 0
         assert r["diag"]["e_energy"] == f["diag"]["e_energy"]
+
+
+def _fronts_128():
+    """Two electron clouds at +-0.6 c along x, each in its own half of a
+    periodic 128^2 box: their fronts sweep through empty tiles, whose particle
+    segments must grow as they fill."""
+    L = 12.8
+    return Workload("clouds_128x128", 128, 128, L, L, 0.07, 600,
+                    [SpeciesSpec(-1.0, 1.0, 0.0, L / 2, (4, 4), (0.05,) * 3, (0.6, 0.0, 0.0)),
+                     SpeciesSpec(-1.0, 1.0, L / 2, L, (4, 4), (0.05,) * 3, (-0.6, 0.0, 0.0))],
+                    seed=0x5EED7300)
+
+
+@pytest.mark.parametrize("static", [False, True])
+def test_batched_steps_keep_the_particle_layouts_growing(static):
+    """A batch member whose tiles fill and empty (moving cloud fronts) over
+    600 batched steps: the batch runs the layout check every 8 steps, and the
+    step end lays out a member whose push found a segment short, so no
+    segment overflows, and the member ends bitwise as when stepped alone."""
+    from paper_2106_12485_amd import batch_step_static
+    w, w2 = _fronts_128(), small_workloads()[1]
+    alone = Simulation(w)
+    alone.step(600)
+    ea = alone.energy()
+    assert ea["status"] == 0
+    sims = [Simulation(w), Simulation(w2)]
+    if static:
+        for _ in range(60):
+            batch_step_static(sims, 10)
+    else:
+        b = Batch(2, sum(s.layout()["ntx"] * s.layout()["nty"] for s in sims))
+        for _ in range(60):
+            b.step(sims, 10)
+    e = sims[0].energy()
+    assert e["status"] == 0 and sims[0].status() == 0 and e["step"] == 600
+    assert e["e_energy"] == ea["e_energy"] and e["b_energy"] == ea["b_energy"]
+    assert np.array_equal(e["n_particles"], ea["n_particles"])
+    assert np.array_equal(sims[0].get_fields(), alone.get_fields())
