@@ -571,6 +571,36 @@ def test_clouds_1024_thousand_steps_without_a_settle():
     assert np.array_equal(e["n_particles"], n0)
 
 
+@pytest.mark.parametrize("deposit", ["reduction", "commutative"])
+def test_timed_steps_match_the_graph_and_time_every_push(deposit):
+    """pic_timing: the same 20 steps launched directly, with HIP events
+    around each kernel class (one push launch with the reduction deposit,
+    five with the commutative one), end with the fields bitwise those of the
+    graph replay (the current sums are exact integers); one push time per
+    step, each positive, their sum below the steps' wall time."""
+    import time
+    import torch
+    w = thermal64()
+    a, b = Simulation(w, deposit=deposit), Simulation(w, deposit=deposit)
+    a.step(20)
+    b.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(20)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    tk = b.timing_read()
+    b.timing(False)
+    ms, n = tk["push_deposit"]
+    assert n == 20 and 0 < ms < wall_ms
+    assert tk["yee"][1] == 20
+    assert np.array_equal(a.get_fields(), b.get_fields())
+    ea, eb = a.energy(), b.energy()
+    assert ea["step"] == eb["step"] == 20 and ea["status"] == eb["status"] == 0
+    assert np.array_equal(ea["n_particles"], eb["n_particles"])
+    np.testing.assert_allclose(eb["ke"], ea["ke"], rtol=1e-12)
+
+
 @pytest.mark.timeout(900)
 def test_lwfa_2000x256_whole_run_energy_and_teacher_forced_steps():
     """The 2000 x 256 laser-wakefield run over its stated 500 steps: total
