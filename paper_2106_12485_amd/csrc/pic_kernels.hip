@@ -1507,34 +1507,35 @@ __device__ __forceinline__ int load_bucket(int w)
     return 63 - min(63, max(0, k));
 }
 
-// The particle layouts of every species of one simulation (relayout_body).
-// One block of NTO threads; ends with a barrier.
+// The particle layout of species s of one simulation (relayout_body).  One
+// block of NTO threads; ends with a barrier.
 template <typename R>
-__device__ void layouts_body(const SimDev<R> &d)
+__device__ void layout_body(const SimDev<R> &d, int s)
 {
     __shared__ long long s_part[NTO / 64];
     __shared__ int s_flag;
-    for (int s = 0; s < d.nsp; ++s) {
-        if (threadIdx.x == 0) s_flag = 0;
-        __syncthreads();
-        relayout_body(d, s, s_part, &s_flag);
-        __syncthreads();
-    }
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    relayout_body(d, s, s_part, &s_flag);
+    __syncthreads();
 }
 
-// The particle layouts, then, with write_order, the push's work order.  One
-// block of NTO threads.
+// The particle layouts of every species, one after another.
 template <typename R>
-__device__ __forceinline__ void order_body(const SimDev<R> &d, bool write_order)
+__device__ void layouts_body(const SimDev<R> &d)
+{
+    for (int s = 0; s < d.nsp; ++s) layout_body(d, s);
+}
+
+// The push's work order from the tiles' counts.  One block of NTO threads.
+template <typename R>
+__device__ __forceinline__ void order_body(const SimDev<R> &d)
 {
     __shared__ int s_wc[NTO / 64][64];
     __shared__ int s_base[64];
     // bucket of every item while they fit (read once, used by both passes)
     constexpr int KB_MAX = 16384;
     __shared__ unsigned char s_kb[KB_MAX];
-    // the particle layouts first (the order reads the same counts)
-    layouts_body(d);
-    if (!write_order) return;
     const int pp = glob(d.st)->ppar, n = d.ntiles * d.nsb;
     const int rows = (n + NTO - 1) / NTO;
     if (threadIdx.x < 64) s_base[threadIdx.x] = 0;
@@ -1611,10 +1612,16 @@ __device__ __forceinline__ void order_body(const SimDev<R> &d, bool write_order)
     }
 }
 
+// Blocks 0 .. nsp-1 lay out the particle segments of species blockIdx.x;
+// block nsp writes the work order.  The parts run side by side: the order
+// reads only the tiles' counts, which a relayout leaves as they are.
 template <typename R>
 __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
 {
-    order_body(d, true);
+    if ((int)blockIdx.x < d.nsp)
+        layout_body(d, (int)blockIdx.x);
+    else
+        order_body(d);
 }
 
 // The particle layouts of every simulation of a batch, one block each.  The
@@ -1623,7 +1630,7 @@ __global__ __launch_bounds__(NTO) void k_order(SimDev<R> d)
 template <typename R>
 __global__ __launch_bounds__(NTO) void k_layout_b(const SimDev<R> *__restrict__ ds)
 {
-    order_body(ds[blockIdx.x], false);
+    layouts_body(ds[blockIdx.x]);
 }
 
 template <typename R, int RF>
@@ -2326,7 +2333,7 @@ hipError_t Launch<R>::push_deposit(const SimDev<R> &d, hipStream_t s)
 template <typename R>
 hipError_t Launch<R>::order(const SimDev<R> &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_order<R>, dim3(1), dim3(NTO), 0, s, d);
+    hipLaunchKernelGGL(k_order<R>, dim3(d.nsp + 1), dim3(NTO), 0, s, d);
     return hipGetLastError();
 }
 
