@@ -202,8 +202,10 @@ int pic_deposit(pic_sim *sim, void *stream);
  * Sec. 4.1, a shift by one cell once the light front has crossed the next
  * cell boundary (iter*dt >= (nshift+1)*dx in double), removing the particles
  * of the column that leaves and loading the column that enters.  Must follow
- * pic_deposit of the same step.  Enqueued on `stream`, not waited for.
- * Errors: PIC_E_ARG (NULL handle), PIC_E_HIP. */
+ * pic_deposit of the same step.  If that deposit found a tile's particle
+ * segment short of a few more steps of the tile's inflow, the end of the step
+ * also lays the segments out anew for the next push.  Enqueued on `stream`,
+ * not waited for.  Errors: PIC_E_ARG (NULL handle), PIC_E_HIP. */
 int pic_field_advance(pic_sim *sim, void *stream);
 
 /* nsteps iterations of the main simulation loop (Sec. 2.2, Fig. 1), each
@@ -211,7 +213,11 @@ int pic_field_advance(pic_sim *sim, void *stream);
  * stay in their outboxes and the next push takes them from there (calls that
  * read particles append them first).  The steps are replayed from HIP graphs
  * captured on first use: one of 8 steps while 8 or more remain, then one of a
- * single step.  nsteps >= 0.  Enqueued on `stream`, not waited for.
+ * single step.  At most every 8 pushes, and before the first push of each
+ * 8-step graph, the particle segments are checked against every tile's count,
+ * growth and inflow and laid out anew if one is short; a tile that still
+ * outgrows its segment drops the excess and pic_status reports
+ * PIC_E_CAPACITY.  nsteps >= 0.  Enqueued on `stream`, not waited for.
  * Errors: PIC_E_ARG (NULL handle, nsteps < 0), PIC_E_HIP. */
 int pic_step(pic_sim *sim, int nsteps, void *stream);
 
