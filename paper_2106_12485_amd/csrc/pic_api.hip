@@ -522,8 +522,7 @@ int enqueue_settle(pic_sim *s, const SimDev<R> &d, hipStream_t st, bool only_if_
 
 // The push's work order (heaviest tiles first) and the particle layout are
 // rewritten at most every GRAPH_STEPS pushes: particle counts move slowly,
-// and the order only has to be close.  (A push that finds a tile's segment
-// short of a few steps of its inflow also has the step end relayout.)
+// and the order only has to be close.
 constexpr int GRAPH_STEPS = GRAPH_STEPS_N;
 
 // The push of one step, preceded by a new work order when `order` is set.
